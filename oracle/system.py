@@ -1,0 +1,166 @@
+"""Assembled FP64 smoothing system (test oracle).
+
+Everything here is a direct transcription of a definition in arXiv:1901.00654,
+assembled with scipy.sparse:
+
+- Phi[i, k] = phi_k(x_i), the tensor-product B-spline basis with multi-indices
+  ordered "descending lexicographically" (Sec. 2.1, eq. 2.2). Reading: j_1 is
+  the most significant digit and j_P the least (C order), the only order under
+  which Phi' is the Khatri-Rao product of the Phi_p' and Psi_r, I are Kronecker
+  products in the natural factor order (Sec. 2.4).
+- Psi^p_r[j, l] = <D^r phi_j, D^r phi_l>_{L2(Omega_p)} (Sec. 2.4), integrated
+  over Omega_p = [lo, hi] by Gauss-Legendre with q+1 nodes per knot interval,
+  exact for the degree-2q integrands.
+- Lambda = sum_{|r|=2} (2/r!) Psi_r, Psi_r = kron_p Psi^p_{r_p} (Sec. 2.2 and
+  2.4). Reading: the matrix form is taken as the definition of the penalty
+  (it is the integrated squared Frobenius norm of the Hessian); the displayed
+  integrand of eq. 2.3 squares the *sum* of the second derivatives instead,
+  which disagrees with the matrix form for P >= 2.
+- A = Phi'Phi + lambda Lambda and b = Phi'y (eq. 2.4).
+- The 1D prolongation I[i, j] = 2^-q binom(q+1, i - 2j + q + 1) (1-based, from
+  the subdivision formula eq. 2.5) and its Kronecker product (eq. 2.6).
+  Reading: entries whose row would fall outside 1..J^h are dropped; those fine
+  B-splines vanish on Omega.
+- Grid hierarchy N_g = 2^g intervals per dimension, K_g = (2^g + q)^P
+  (Sec. 3.2.1), A_g = Phi_g'Phi_g + lambda Lambda_g with Phi_g evaluated at
+  the same data points on every level.
+
+Pins live in tests/test_oracle_system.py and tests/test_oracle_transfer.py.
+"""
+import itertools
+import math
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import bspline
+
+
+def num_coeffs(N, q, d):
+    """K = prod_p J_p with J_p = N + q (Sec. 2.1; Table 1 for J_p = 35)."""
+    return (N + q) ** d
+
+
+def phi_matrix(x, lo, hi, N, q=3):
+    """Sparse Phi (n x K) for points x (n x d) on [lo, hi]^d, N intervals per dim.
+
+    Row i is the Kronecker product over dimensions of the 1D rows
+    Phi_p[i, :] (the Khatri-Rao identity of Sec. 2.4), built entry by entry.
+    """
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    n, d = x.shape
+    J = N + q
+    cells, vals = [], []
+    for p in range(d):
+        c, V = bspline.basis_local(x[:, p], lo[p], hi[p], N, q)
+        cells.append(c)
+        vals.append(V)
+    rows, cols, data = [], [], []
+    for a in itertools.product(range(q + 1), repeat=d):
+        col = np.zeros(n, dtype=np.int64)
+        val = np.ones(n)
+        for p in range(d):
+            col = col * J + (cells[p] + a[p])
+            val = val * vals[p][:, a[p]]
+        rows.append(np.arange(n))
+        cols.append(col)
+        data.append(val)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    data = np.concatenate(data)
+    return sp.csr_matrix((data, (rows, cols)), shape=(n, J ** d))
+
+
+def gram_1d(lo, hi, N, q, r):
+    """Dense Psi_r (J x J) on [lo, hi]: integral of D^r B_j * D^r B_l."""
+    J = N + q
+    h = (hi - lo) / N
+    nodes, weights = np.polynomial.legendre.leggauss(q + 1)
+    G = np.zeros((J, J))
+    for c in range(N):
+        a, b = lo + c * h, lo + (c + 1) * h
+        xq = 0.5 * (a + b) + 0.5 * (b - a) * nodes
+        wq = 0.5 * (b - a) * weights
+        D = bspline.basis_dense(xq, lo, hi, N, q, r)   # (q+1 nodes) x J
+        G += D.T @ (wq[:, None] * D)
+    return G
+
+
+def lambda_matrix(d, lo, hi, N, q=3):
+    """Lambda = sum over multi-indices r with |r| = 2 of (2/r!) kron_p Psi^p_{r_p}."""
+    psi = [[sp.csr_matrix(gram_1d(lo[p], hi[p], N, q, rp)) for rp in range(3)]
+           for p in range(d)]
+    J = N + q
+    L = sp.csr_matrix((J ** d, J ** d))
+    for r in itertools.product(range(3), repeat=d):
+        if sum(r) != 2:
+            continue
+        coef = 2.0 / np.prod([math.factorial(rp) for rp in r])
+        term = psi[0][r[0]]
+        for p in range(1, d):
+            term = sp.kron(term, psi[p][r[p]], format="csr")
+        L = L + coef * term
+    return L.tocsr()
+
+
+def system(x, y, lo, hi, N, lam, q=3):
+    """(A, b, Phi, Lambda) with A = Phi'Phi + lam Lambda, b = Phi'y (eq. 2.4)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    d = x.shape[1]
+    Phi = phi_matrix(x, lo, hi, N, q)
+    Lam = lambda_matrix(d, lo, hi, N, q)
+    A = (Phi.T @ Phi + lam * Lam).tocsr()
+    b = Phi.T @ np.asarray(y, dtype=np.float64)
+    return A, b, Phi, Lam
+
+
+def prolongation_1d(Nc, q=3):
+    """I_{2h}^h (J^h x J^{2h}) from the subdivision formula (eq. 2.5).
+
+    1-based: I[i, j] = 2^-q binom(q+1, i - 2j + q + 1) for 0 <= i-2j+q+1 <= q+1.
+    """
+    Jc, Jf = Nc + q, 2 * Nc + q
+    I = np.zeros((Jf, Jc))
+    for i in range(1, Jf + 1):
+        for j in range(1, Jc + 1):
+            m = i - 2 * j + q + 1
+            if 0 <= m <= q + 1:
+                I[i - 1, j - 1] = math.comb(q + 1, m) / 2.0 ** q
+    return I
+
+
+def prolongation(d, Nc, q=3):
+    """Multivariate I_{2h}^h = kron_p I_p (eq. 2.6), sparse."""
+    I1 = sp.csr_matrix(prolongation_1d(Nc, q))
+    P = I1
+    for _ in range(1, d):
+        P = sp.kron(P, I1, format="csr")
+    return P
+
+
+def level_intervals(N, G):
+    """N_g for g = 1..G given the finest N = N_G (Sec. 3.2.1: N_g = 2^g)."""
+    return [N >> (G - g) for g in range(1, G + 1)]
+
+
+def hierarchy(x, y, lo, hi, N, lam, q=3, G=None):
+    """Per-level assembled data, finest level G: N_G = N, N_g = N / 2^(G-g).
+
+    Returns a dict g -> {"N", "A", "b", "Phi", "Lam", "P"} where P is the
+    prolongation from level g-1 to g (absent at g = 1).
+    """
+    if G is None:
+        G = int(round(math.log2(N)))
+    levels = {}
+    for g, Ng in zip(range(1, G + 1), level_intervals(N, G)):
+        A, b, Phi, Lam = system(x, y, lo, hi, Ng, lam, q)
+        lev = {"N": Ng, "A": A, "b": b, "Phi": Phi, "Lam": Lam}
+        if g > 1:
+            lev["P"] = prolongation(np.atleast_2d(x).shape[1], Ng // 2, q)
+        levels[g] = lev
+    return levels
+
+
+def evaluate(alpha, xq, lo, hi, N, q=3):
+    """s(x) = sum_k alpha_k phi_k(x) at query points (eq. 2.2)."""
+    return phi_matrix(xq, lo, hi, N, q) @ np.asarray(alpha, dtype=np.float64)

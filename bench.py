@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free multigrid-preconditioned spline smoother.
+
+One step = the whole hot path on the d=3 clustered workload (64^3 knot
+intervals, 300,763 coefficients, 2,000,000 points from a Gaussian mixture,
+lambda = 1e-5) with the points already resident on the GPU: problem setup
+(binning and sort, Jacobi diagonals, Lanczos damping, coarse assembly and
+inversion), MGCG to a relative FP64 residual of 1e-8, and evaluation of the
+fit at every data point.
+
+Prints one JSON line: solves/s (value), the roofline of the dominant kernel
+(the point pass of the finest-level operator apply, timed with HIP events on
+its stream inside the library), the operator-apply rate for d = 2..5 at the
+full workload sizes, the other precision mode for comparison, and the CPU
+oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PCG time-to-1e-8 residual + operator-apply GB/s (d=2–5); served solves/s, p99"
+PEAK_FP64_VALU_TFLOPS = 78.6     # 256 CUs x 2.4 GHz x 64 lanes x 2 (FMA)
+PEAK_HBM_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_data_c2.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1901_00654_amd", "csrc", "kernels.hip")
+
+
+def algorithmic(d, n, K, fp32):
+    """FLOP and bytes one point pass must spend: per point the d*4 cubic values
+    (15 d FLOP), the tensor product (4^d), gather (2 * 4^d) and scatter
+    (2 * 4^d); per point its d cell coordinates and cell index; per
+    coefficient one read of c and one write of the output."""
+    s = 4 if fp32 else 8
+    flops = n * (5 * 4 ** d + 15 * d)
+    nbytes = n * (d * s + 4) + 2 * K * s
+    return flops, nbytes
+
+
+def source_hash():
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_bytes():
+    """HBM bytes per launch of the point pass from the committed rocprofv3
+    counter summary, or None if absent or taken on another kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except ValueError:
+        return None
+    if t.get("kernel_source_sha256_16") != source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def make_problem(tsmg, w, xd, yd, stream, precision, tol=1e-8):
+    opt = tsmg.ts_default_options()
+    opt.stream = stream.cuda_stream
+    opt.tol = tol
+    opt.precision = precision
+    opt.max_iter = 100000
+    d = w["d"]
+    return tsmg.ts_create(d, 3, [w["N"]] * d, w["lo"], w["hi"], len(w["y"]), xd, yd, w["lam"], opt)
+
+
+def run_steps(tsmg, torch, w, xd, yd, stream, precision, steps, warmup):
+    K = (w["N"] + 3) ** w["d"]
+    n = len(w["y"])
+    alpha = torch.empty(K, dtype=torch.float64, device="cuda")
+    yq = torch.empty(n, dtype=torch.float64, device="cuda")
+    infos = []
+
+    def step():
+        h = make_problem(tsmg, w, xd, yd, stream, precision)
+        try:
+            status, info = tsmg.ts_solve(h, alpha)
+            if status != tsmg.TS_OK:
+                raise RuntimeError("solve did not converge: %s" % info.as_dict())
+            tsmg.ts_evaluate(h, alpha, n, xd, yq)
+        finally:
+            tsmg.ts_destroy(h)
+        return info.as_dict()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps, infos, alpha
+
+
+def apply_rate(tsmg, torch, w, stream, reps):
+    """Operator-apply rate at one workload: HIP-event times of the Lambda
+    passes and the point pass, FP64 and FP32, as algorithmic GB/s and FLOP/s."""
+    xd = torch.from_numpy(w["x"]).cuda()
+    yd = torch.from_numpy(w["y"]).cuda()
+    torch.cuda.synchronize()
+    h = make_problem(tsmg, w, xd, yd, stream, tsmg.TS_FP64)
+    out = {"workload": w["name"], "d": w["d"], "N": w["N"], "n": len(w["y"])}
+    try:
+        G = tsmg.ts_num_levels(h)
+        K = tsmg.ts_num_coeffs(h, G)
+        for fp32 in (False, True):
+            tsmg.ts_profile_apply(h, G, fp32, 2)
+            ms_l, ms_d = tsmg.ts_profile_apply(h, G, fp32, reps)
+            fl, by = algorithmic(w["d"], len(w["y"]), K, fp32)
+            s = 4 if fp32 else 8
+            by_total = by + 2 * K * s * w["d"]      # Lambda passes stream the tensors too
+            t = (ms_l + ms_d) * 1e-3
+            tag = "fp32" if fp32 else "fp64"
+            out[tag] = {"ms_apply": ms_l + ms_d, "ms_point_pass": ms_d, "ms_lambda": ms_l,
+                        "apply_GBps": by_total / t / 1e9,
+                        "point_pass_TFLOPs": fl / (ms_d * 1e-3) / 1e12,
+                        "point_pass_frac_fp64_valu": fl / (ms_d * 1e-3) / 1e12 / PEAK_FP64_VALU_TFLOPS}
+    finally:
+        tsmg.ts_destroy(h)
+        del xd, yd
+    return out
+
+
+def cpu_baseline(w, applies_per_solve, budget_s=20.0):
+    """The oracle's matrix-free FP64 apply (NumPy) on the same points, timed
+    for about budget_s seconds, scaled to solves/s with the number of operator
+    applies one GPU solve performed."""
+    import numpy as np
+    from oracle import matfree
+    c = np.random.default_rng(0).standard_normal((w["N"] + 3) ** w["d"])
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        matfree.apply(w["x"], c, w["lo"], w["hi"], w["N"], w["lam"])
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s or len(times) >= 5:
+            break
+    t_apply = float(np.median(times))
+    est_solve = t_apply * applies_per_solve
+    return {"value": 1.0 / est_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": ("oracle matfree.apply (FP64 NumPy, single thread) on the full %s points, "
+                       "%d timed applies, median %.2f s each, times %d applies per solve taken "
+                       "from the GPU run; setup and V-cycle vector work not counted"
+                       % (w["name"], len(times), t_apply, applies_per_solve)),
+            "host_cpus": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--reps", type=int, default=20, help="timed launches per apply measurement")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the d=2..5 apply sweep")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1901_00654_amd import tsmg, workloads
+
+    tsmg.load_library()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    w = workloads.c2()
+    xd = torch.from_numpy(w["x"]).cuda()
+    yd = torch.from_numpy(w["y"]).cuda()
+    torch.cuda.synchronize()
+    prec = tsmg.TS_FP64 if args.precision == "fp64" else tsmg.TS_MIXED_FP32
+    sec, infos, alpha = run_steps(tsmg, torch, w, xd, yd, stream, prec, args.steps, args.warmup)
+    info = infos[-1]
+
+    # roofline of the dominant kernel: the finest-level point pass, FP64
+    h = make_problem(tsmg, w, xd, yd, stream, tsmg.TS_FP64)
+    try:
+        G = tsmg.ts_num_levels(h)
+        K = tsmg.ts_num_coeffs(h, G)
+        fp32 = prec != tsmg.TS_FP64 and False
+        tsmg.ts_profile_apply(h, G, fp32, 2)
+        ms_lam, ms_data = tsmg.ts_profile_apply(h, G, fp32, args.reps)
+    finally:
+        tsmg.ts_destroy(h)
+    flops, nbytes = algorithmic(w["d"], len(w["y"]), K, False)
+    t_data = ms_data * 1e-3
+    achieved = flops / t_data / 1e12
+    tr = traffic_bytes()
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": tr,
+                "kernel": "k_data<3,double,apply> (point pass, finest level)",
+                "ms_per_launch": ms_data, "algorithmic_flop": flops, "algorithmic_bytes": nbytes,
+                "algorithmic_GBps": nbytes / t_data / 1e9}
+
+    result = {
+        "metric": METRIC, "value": 1.0 / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == tsmg.TS_FP64 else "f32+f64",
+        "data": "synthetic (seeded Gaussian mixture, see workloads.c2)",
+        "config": {"workload": "c2: d=3 cubic, 64^3 intervals (K=300763), n=2,000,000 clustered points, "
+                               "lambda=1e-5, MGCG to rel. FP64 residual 1e-8",
+                   "precision": args.precision, "nu": 2, "levels": G},
+        "time_to_tol_s": info["solve_s"], "setup_s": info["setup_s"], "iterations": info["iterations"],
+        "refinements": info["refinements"], "rel_residual": info["rel_residual"],
+        "applies_per_solve": info["applies"], "roofline": roofline,
+        "lambda_passes_ms": ms_lam,
+    }
+
+    if not args.no_compare:
+        other = tsmg.TS_MIXED_FP32 if prec == tsmg.TS_FP64 else tsmg.TS_FP64
+        sec2, infos2, alpha2 = run_steps(tsmg, torch, w, xd, yd, stream, other, max(1, args.steps // 2), 0)
+        diff = float(torch.linalg.norm(alpha2 - alpha) / torch.linalg.norm(alpha))
+        result["other_precision"] = {"precision": "mixed" if other != tsmg.TS_FP64 else "fp64",
+                                     "solves_per_s": 1.0 / sec2, "iterations": infos2[-1]["iterations"],
+                                     "refinements": infos2[-1]["refinements"],
+                                     "rel_residual": infos2[-1]["rel_residual"],
+                                     "rel_diff_vs_headline_alpha": diff}
+    del xd, yd
+    torch.cuda.empty_cache()
+
+    if not args.no_sweep:
+        sweep = []
+        for name in ("c1", "c2", "c3", "c4"):
+            wk = w if name == "c2" else workloads.CONFIGS[name]()
+            sweep.append(apply_rate(tsmg, torch, wk, stream, args.reps))
+            torch.cuda.empty_cache()
+        result["apply_sweep"] = sweep
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_calibration_bytes"] = src.numel() * 8
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(w, info["applies"])
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

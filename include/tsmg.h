@@ -1,0 +1,221 @@
+/*
+ * tsmg.h — C ABI of the MI355X (gfx950) matrix-free multigrid-preconditioned
+ * tensor-product spline smoother of arXiv:1901.00654.
+ *
+ * The library solves the normal equations of penalised tensor-product
+ * B-spline smoothing (Sec. 2.2, eq. 2.4)
+ *
+ *     (Phi' Phi + lambda Lambda) alpha = Phi' y
+ *
+ * for scattered data {(x_i, y_i)} in [lo, hi]^d, cubic B-splines (q = 3) on
+ * N uniform knot intervals per dimension, without assembling the matrix:
+ * Phi'Phi is applied point by point (the Khatri-Rao products of Alg. 3/4) and
+ * Lambda through its Kronecker structure (Alg. 2). CG is preconditioned by one
+ * geometric multigrid V-cycle (Alg. 7) over the levels g = 1..G,
+ * N_g = 2^g (Sec. 3.2.1), with damped Jacobi smoothing (Alg. 6), subdivision
+ * prolongation and its transpose (Sec. 3.2.3) and an exact coarse solve on
+ * g = 1 (Sec. 3.2.4); the outer loop is Alg. 8.
+ *
+ * Conventions shared by every call:
+ * - Coefficient vectors of level g hold K_g = (N_g + 3)^d entries in C order:
+ *   the multi-index (j_1, ..., j_d), 0 <= j_p < N_g + 3, maps to
+ *   k = sum_p j_p (N_g + 3)^(d-1-p), j_d contiguous (the "descending
+ *   lexicographical order" of Sec. 2.1).
+ * - Vector arguments are DEVICE pointers owned by the caller, allocated with
+ *   at least the stated length, on the device that was current at ts_create.
+ *   Work is enqueued on the problem's stream (ts_options.stream, or a stream
+ *   the library creates when that is NULL); calls return once it is enqueued
+ *   unless stated otherwise. The caller must not free or modify an argument
+ *   before that stream has consumed it.
+ * - Every call returns a ts_status. Negative values are errors: the call had
+ *   no effect on its outputs beyond what it may have enqueued, and
+ *   ts_last_error() gives a message (thread-local, valid until the next
+ *   failing call on the same thread). No C++ exception crosses this ABI.
+ * - A ts_problem is not thread-safe; distinct problems are independent.
+ * - There is one GPU code path per precision and no CPU fallback: if the
+ *   device or a kernel is unavailable the call fails with TS_EDEVICE.
+ */
+#ifndef TSMG_H
+#define TSMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ts_problem ts_problem;
+
+typedef enum {
+    TS_OK = 0,
+    TS_ENOTCONV = 1,      /* iteration limit reached; outputs hold the last iterate */
+    TS_EINVAL = -1,       /* an argument is out of range (message says which)       */
+    TS_ENOMEM = -2,       /* device allocation failed                               */
+    TS_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed             */
+    TS_ESINGULAR = -4,    /* the coarse matrix A_1 is not positive definite, i.e.
+                             an affine function vanishes at every data point and
+                             the smoothing problem has no unique solution          */
+    TS_EBREAKDOWN = -5    /* CG breakdown: p'Ap <= 0 or a non-finite scalar        */
+} ts_status;
+
+typedef enum {
+    TS_FP64 = 0,          /* every operation in FP64                                 */
+    TS_MIXED_FP32 = 1,    /* FP64 residuals in an iterative-refinement loop around a
+                             PCG whose applies and V-cycle run in FP32; FP64 only for
+                             inner products, the refinement residual and the coarse
+                             solve                                                   */
+    TS_MIXED_BF16 = 2     /* reserved: bfloat16 storage of the per-point 1D basis values
+                             of the inner operator; not available in this version
+                             (TS_EINVAL)                                              */
+} ts_precision;
+
+typedef struct {
+    int nu1, nu2;          /* pre/post Jacobi sweeps per level (Alg. 7); default 2, 2 */
+    double omega_scale;    /* omega_g = omega_scale / theta_g, theta_g the largest
+                              Ritz value of lanczos_steps Lanczos steps on
+                              D_g^-1/2 A_g D_g^-1/2; default 1.5, must be in (0, 2)  */
+    int lanczos_steps;     /* default 16                                             */
+    double omega_fixed;    /* > 0: use this omega on every level instead             */
+    ts_precision precision;/* used by ts_solve; default TS_FP64                       */
+    int max_iter;          /* outer CG iterations (FP64) or total inner iterations
+                              (mixed); default 10000                                 */
+    double tol;            /* stop when ||b - A alpha||_2 / ||b||_2 <= tol; 1e-8       */
+    double inner_tol;      /* mixed: relative reduction per refinement step; 1e-4     */
+    int max_refine;        /* mixed: refinement steps; default 50                    */
+    int points_per_block;  /* data-term work per workgroup; 0 = automatic            */
+    void* stream;          /* hipStream_t to enqueue on; NULL = a library stream      */
+} ts_options;
+
+typedef struct {
+    int iterations;        /* CG iterations (FP64) or inner PCG iterations (mixed)   */
+    int refinements;       /* mixed: outer refinement steps; FP64: 0                 */
+    int converged;         /* 1 if rel_residual <= tol                                */
+    double rel_residual;   /* ||b - A alpha||_2 / ||b||_2 recomputed in FP64 at exit  */
+    double setup_s;        /* wall time of ts_create                                 */
+    double solve_s;        /* wall time of this ts_solve                             */
+    int64_t applies;       /* operator applies (any level, any precision) performed  */
+} ts_solve_info;
+
+/* Fills *opt with the defaults listed above. */
+void ts_default_options(ts_options* opt);
+
+/* Library version string, e.g. "tsmg 0.1 gfx950". */
+const char* ts_version(void);
+
+/*
+ * Creates a smoothing problem (Sec. 2.2) and runs all setup on the device:
+ * bins and sorts the points by knot cell, builds the level hierarchy
+ * g = 1..G with G = log2(N) (Sec. 3.2.1), the Jacobi diagonals (Alg. 5 plus
+ * the Kronecker diagonal of Lambda, Sec. 3.2.2), the damping omega_g, the
+ * coarse matrix A_1 and its inverse (Sec. 3.2.4).
+ *   d          dimension, 1 <= d <= 5
+ *   q          spline degree; must be 3
+ *   intervals  d ints, knot intervals per dimension; all equal to one power of
+ *              two N with 2 <= N and (N + 3)^d < 2^31 and N^d <= 2^30
+ *   lo, hi     d doubles (host), the box [lo_p, hi_p], lo_p < hi_p
+ *   n          number of points, n >= 1
+ *   x          device, n*d doubles, row-major (point i at x[i*d .. i*d+d-1]);
+ *              every x must be finite and inside the box
+ *   y          device, n doubles, finite
+ *   lambda     smoothing weight, finite and > 0
+ *   opt        options (NULL = defaults); copied
+ *   out        receives the handle
+ * x and y are copied into library-owned storage and not retained. Returns
+ * TS_EINVAL for bad arguments (including points outside the box or non-finite
+ * data), TS_ESINGULAR if A_1 is not positive definite, TS_ENOMEM, TS_EDEVICE.
+ * Synchronises the stream before returning.
+ */
+ts_status ts_create(int d, int q, const int32_t* intervals, const double* lo,
+                    const double* hi, int64_t n, const double* x, const double* y,
+                    double lambda, const ts_options* opt, ts_problem** out);
+
+/* Releases every resource of the problem (synchronises its stream). NULL is a no-op. */
+void ts_destroy(ts_problem* p);
+
+/* Replaces the solve-time options of a problem: nu1, nu2, precision, max_iter,
+ * tol, inner_tol and max_refine. Setup-time fields (omega_scale, lanczos_steps,
+ * omega_fixed, points_per_block, stream) are ignored. Returns TS_EINVAL for
+ * negative smoothing counts, tol <= 0 or an unknown precision. */
+ts_status ts_set_options(ts_problem* p, const ts_options* opt);
+
+/* Number of levels G (finest level index). */
+ts_status ts_num_levels(const ts_problem* p, int* G);
+
+/* K_g = (N_g + 3)^d for level 1 <= g <= G (Sec. 3.2.1). */
+ts_status ts_num_coeffs(const ts_problem* p, int level, int64_t* K);
+
+/* The damping omega_g used by the Jacobi smoother on level g (2 <= g <= G; level 1
+ * is solved exactly and reports 0). */
+ts_status ts_get_omega(const ts_problem* p, int level, double* omega);
+
+/* b = Phi_G' y on the finest level (Alg. 3; first line of Alg. 8). b: device, K_G doubles. */
+ts_status ts_rhs(ts_problem* p, double* b);
+
+/* out = A_g c = (Phi_g'Phi_g + lambda Lambda_g) c (Alg. 4 then Alg. 3, plus Alg. 2 over
+ * the Kronecker terms of Lambda, Sec. 2.4). c, out: device, K_g doubles, must not
+ * alias. */
+ts_status ts_apply(ts_problem* p, int level, const double* c, double* out);
+
+/* The same operator evaluated in FP32 arithmetic (the inner operator of the mixed
+ * modes; basis values from FP32 cell coordinates). c, out: device, K_g floats. */
+ts_status ts_apply_f32(ts_problem* p, int level, const float* c, float* out);
+
+/* D = diag(A_g) (Alg. 5 for Phi_g'Phi_g plus lambda diag(Lambda_g), Sec. 3.2.2).
+ * D: device, K_g doubles. */
+ts_status ts_diag(ts_problem* p, int level, double* D);
+
+/* out = I_{g-1}^{g} e: prolongation from level g-1 to g by the subdivision matrix
+ * (eq. 2.6), 2 <= g <= G. e: device K_{g-1} doubles; out: device K_g doubles. */
+ts_status ts_prolong(ts_problem* p, int level, const double* e, double* out);
+
+/* out = (I_{g-1}^{g})' r: restriction from level g to g-1 (Sec. 3.2.3), 2 <= g <= G.
+ * r: device K_g doubles; out: device K_{g-1} doubles. */
+ts_status ts_restrict(ts_problem* p, int level, const double* r, double* out);
+
+/* x = A_1^-1 b on the coarsest level (Sec. 3.2.4). b, x: device, K_1 doubles. */
+ts_status ts_coarse_solve(ts_problem* p, const double* b, double* x);
+
+/* z = one V-cycle (Alg. 7) applied to r from a zero start on the finest level, i.e.
+ * the preconditioner of Alg. 8 (FP64). r, z: device, K_G doubles, must not alias. */
+ts_status ts_vcycle(ts_problem* p, const double* r, double* z);
+
+/* The same V-cycle in FP32 (coarse solve still in FP64). r, z: device, K_G floats. */
+ts_status ts_vcycle_f32(ts_problem* p, const float* r, float* z);
+
+/*
+ * Solves (Phi'Phi + lambda Lambda) alpha = Phi'y by Alg. 8 (TS_FP64) or by
+ * FP64 iterative refinement around an FP32 Alg. 8 (mixed modes), to the
+ * relative FP64 residual opt.tol.
+ *   alpha  device, K_G doubles; on entry the start vector when use_start != 0
+ *          (else ignored and zero is used); on exit the solution
+ *   info   may be NULL
+ * Returns TS_OK, TS_ENOTCONV (limit reached, alpha holds the last iterate),
+ * TS_EBREAKDOWN, or an error. Synchronises the stream.
+ */
+ts_status ts_solve(ts_problem* p, double* alpha, int use_start, ts_solve_info* info);
+
+/* yq[i] = s(xq_i) = sum_k alpha_k phi_k(xq_i) (eq. 2.2) at m query points.
+ * alpha: device K_G doubles; xq: device m*d doubles row-major; yq: device m doubles.
+ * Points outside the box are evaluated on the polynomial piece of the nearest
+ * boundary cell. Synchronises the stream. */
+ts_status ts_evaluate(ts_problem* p, const double* alpha, int64_t m, const double* xq,
+                      double* yq);
+
+/* Measurement of the operator apply A_g c (no effect on the problem's state):
+ * enqueues `reps` back-to-back launches of the lambda Lambda_g passes, then
+ * `reps` launches of the point pass (Phi_g'Phi_g c, the data-term kernel), on
+ * internal vectors filled with a fixed pattern, and reports the average
+ * duration of one of each in milliseconds, timed with HIP events recorded on
+ * the problem's stream. fp32 != 0 times the FP32 operator. Synchronises. */
+ts_status ts_profile_apply(ts_problem* p, int level, int fp32, int reps, double* ms_lambda,
+                           double* ms_data);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ts_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSMG_H */

@@ -1,0 +1,35 @@
+// Shared definitions of the tsmg device kernels and their host launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tsmg {
+
+constexpr int kMaxDim = 5;
+constexpr int kDeg = 3;          // cubic B-splines
+constexpr int kBlock = 256;      // threads per workgroup for every kernel
+
+// What the point pass of the data term computes (Alg. 3/4/5):
+enum DataMode : int {
+  kApply = 0,   // out += Phi'(Phi c)           gather then scatter
+  kRhs = 1,     // out += Phi' y                scatter of the responses
+  kDiag = 2,    // out += sum_i v_i[k]^2        Alg. 5
+};
+
+// Per-launch description of one level of one problem for the point pass.
+struct DataArgs {
+  const void* tfrac;        // [d][n] T: position inside the finest knot cell, in [0,1]
+  const uint32_t* cell;     // [n] finest-level cell, C order (N_G^(d-1-p) weights)
+  const uint32_t* mkey;     // [n] finest-level cell, Morton order (the sort key)
+  const double* y;          // [n] responses (kRhs only)
+  const int32_t* off;       // [N_G^d + 1] first sorted point of each finest Morton cell
+  const void* c;            // [K_g] T, coefficient vector (kApply only)
+  void* out;                // [K_g] T, accumulated atomically
+  int64_t n;                // number of points
+  int G;                    // finest level (N_G = 2^G)
+  int g;                    // this level
+  int tb;                   // tile side 2^tb level-g cells per dimension (tb <= g)
+  int ppb;                  // points per workgroup (<= 2048)
+};
+
+}  // namespace tsmg

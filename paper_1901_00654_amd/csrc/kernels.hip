@@ -1,0 +1,1293 @@
+// Device kernels of tsmg for gfx950 (CDNA4, wave64).
+//
+// Hot path (per operator apply A_g c, Sec. 2.4 / Alg. 2-4 of arXiv:1901.00654):
+//   k_lambda_pass  out  = lambda Lambda_g c, one banded pass per dimension
+//   k_data<kApply> out += Phi_g'(Phi_g c), points sorted by knot cell,
+//                  coefficient patch of a cell tile staged in LDS, per-point
+//                  tensor basis as products of 1D cubic values in registers,
+//                  scatter reduced in LDS before one atomic per patch entry.
+// V-cycle pieces: Jacobi epilogues (Alg. 6), subdivision prolongation and
+// restriction passes (Sec. 3.2.3), coarse GEMV with the precomputed inverse
+// (Sec. 3.2.4); CG vector kernels with device-resident scalars (Alg. 8).
+// Setup: binning, offsets, Jacobi diagonal (Alg. 5 + Kronecker diagonal),
+// coarse assembly by polynomial moments, Gauss-Jordan inversion.
+#include "common.h"
+#include "launch.h"
+
+namespace tsmg {
+
+// ---------------------------------------------------------------------------
+// Cubic uniform B-spline pieces on one knot interval, t in [0,1]: the four
+// functions alive there (indices c..c+3 of the cell c), written out from the
+// de Boor recursion on uniform knots.
+template <typename T>
+__device__ __forceinline__ void cubic_basis(T t, T (&b)[4]) {
+  const T s = T(1) - t;
+  const T t2 = t * t, s2 = s * s;
+  const T t3 = t2 * t, s3 = s2 * s;
+  const T sixth = T(1.0 / 6.0), two3 = T(2.0 / 3.0), half = T(0.5);
+  b[0] = s3 * sixth;
+  b[1] = two3 - t2 + half * t3;
+  b[2] = two3 - s2 + half * s3;
+  b[3] = t3 * sixth;
+}
+
+template <typename T>
+__device__ __forceinline__ T sel4(const T (&b)[4], int a) {
+  T r = b[0];
+  r = (a == 1) ? b[1] : r;
+  r = (a == 2) ? b[2] : r;
+  r = (a == 3) ? b[3] : r;
+  return r;
+}
+
+// Morton (bit-interleaved) index -> per-dimension coordinates, `bits` bits
+// per dimension, dimension 0 most significant inside each bit group.
+template <int D>
+__device__ __forceinline__ void morton_decode(uint32_t key, int bits, int (&c)[D]) {
+#pragma unroll
+  for (int p = 0; p < D; ++p) c[p] = 0;
+  for (int b = 0; b < bits; ++b) {
+#pragma unroll
+    for (int p = 0; p < D; ++p) c[p] |= int((key >> (b * D + (D - 1 - p))) & 1u) << b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Unrolled tensor-product gather / scatter over the innermost dimensions
+// p..D-1 of a patch with strides st[] (last stride 1). Gather is sum-factorised
+// (innermost 4-term rows first); scatter multiplies the weight down the same
+// tree and adds into LDS with hardware atomics.
+template <int D, int p, typename T>
+struct Inner {
+  static __device__ __forceinline__ T gather(const T* lc, int o, const T (&B)[D][4],
+                                             const int (&st)[D]) {
+    T r = T(0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) r += B[p][a] * Inner<D, p + 1, T>::gather(lc, o + a * st[p], B, st);
+    return r;
+  }
+  static __device__ __forceinline__ void scatter(T* acc, int o, const T (&B)[D][4],
+                                                 const int (&st)[D], T w) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) Inner<D, p + 1, T>::scatter(acc, o + a * st[p], B, st, w * B[p][a]);
+  }
+  static __device__ __forceinline__ void scatter_sq(T* acc, int o, const T (&B)[D][4],
+                                                    const int (&st)[D], T w) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      Inner<D, p + 1, T>::scatter_sq(acc, o + a * st[p], B, st, w * B[p][a] * B[p][a]);
+  }
+};
+template <int D, typename T>
+struct Inner<D, D, T> {
+  static __device__ __forceinline__ T gather(const T* lc, int o, const T (&)[D][4], const int (&)[D]) {
+    return lc[o];
+  }
+  static __device__ __forceinline__ void scatter(T* acc, int o, const T (&)[D][4], const int (&)[D], T w) {
+    atomicAdd(&acc[o], w);
+  }
+  static __device__ __forceinline__ void scatter_sq(T* acc, int o, const T (&)[D][4], const int (&)[D], T w) {
+    atomicAdd(&acc[o], w);
+  }
+};
+
+// Dimensions 1..D-1 are unrolled at compile time for D = 5 and dimension 0
+// runs as a 4-step loop that rotates its four basis values through fixed
+// registers, so no array is ever indexed at run time (which would put the
+// basis values in scratch memory). For D <= 4 everything is unrolled.
+template <int D>
+struct Split {
+  static constexpr int L = (D <= 4) ? 0 : 1;
+};
+
+template <int D, typename T>
+__device__ __forceinline__ T patch_gather(const T* lc, int base, const T (&B)[D][4], const int (&st)[D]) {
+  if constexpr (Split<D>::L == 0) {
+    return Inner<D, 0, T>::gather(lc, base, B, st);
+  } else {
+    T s = T(0);
+    T r0 = B[0][0], r1 = B[0][1], r2 = B[0][2], r3 = B[0][3];
+    int o = base;
+#pragma unroll 1
+    for (int a = 0; a < 4; ++a) {
+      s += r0 * Inner<D, 1, T>::gather(lc, o, B, st);
+      r0 = r1; r1 = r2; r2 = r3;
+      o += st[0];
+    }
+    return s;
+  }
+}
+
+template <int D, typename T, bool SQ>
+__device__ __forceinline__ void patch_scatter(T* acc, int base, const T (&B)[D][4], const int (&st)[D], T w0) {
+  if constexpr (Split<D>::L == 0) {
+    if constexpr (SQ) Inner<D, 0, T>::scatter_sq(acc, base, B, st, w0);
+    else Inner<D, 0, T>::scatter(acc, base, B, st, w0);
+  } else {
+    T r0 = B[0][0], r1 = B[0][1], r2 = B[0][2], r3 = B[0][3];
+    int o = base;
+#pragma unroll 1
+    for (int a = 0; a < 4; ++a) {
+      const T w = SQ ? w0 * r0 * r0 : w0 * r0;
+      if constexpr (SQ) Inner<D, 1, T>::scatter_sq(acc, o, B, st, w);
+      else Inner<D, 1, T>::scatter(acc, o, B, st, w);
+      r0 = r1; r1 = r2; r2 = r3;
+      o += st[0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The data term of one level: out += Phi_g'(Phi_g c) (kApply), Phi_g'y (kRhs)
+// or diag(Phi_g'Phi_g) (kDiag).
+//
+// Work split. Workgroup w owns the sorted points [w*ppb, (w+1)*ppb). Points
+// are in Morton order of their finest cell, so each Morton-aligned tile of
+// 2^tb level-g cells per dimension is one contiguous point range. Per tile
+// segment the workgroup stages the (2^tb + 3)^D coefficient patch in LDS and
+// cuts the segment into items: runs of at most Q points of one cell.
+//
+// Items go to lane groups of L = 4^(D-2) lanes (one lane for D <= 2). A
+// lane holds 16 coefficients of the cell's 4^D patch in registers - the last
+// two dimensions, for its own fixed leading multi-index - and 16
+// accumulators. Per point the group evaluates the cubic pieces (the lane's
+// own factor of the leading dimensions by Horner, the four values of each
+// of the last two dimensions), gathers s = v'c (sum-factorised, then summed
+// over the group by shuffles) and scatters s v into its accumulators. After
+// the item, the accumulators are added into the tile's LDS accumulator, and
+// after the tile, the LDS accumulator is added to the output with one
+// global atomic per nonzero entry.
+// Exclusive prefix sum over the workgroup (one value per thread); *total gets
+// the sum. Contains __syncthreads: every thread must call it.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wave_sums[wid] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const int sw = wave_sums[w];
+    before += (w < wid) ? sw : 0;
+    tot += sw;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + x - v;
+}
+
+template <int D>
+struct Group {
+  static constexpr int L = (D <= 2) ? 1 : (1 << (2 * (D - 2)));   // lanes per item
+  static constexpr int V = (D == 1) ? 4 : 16;                      // coefficients per lane
+  static constexpr int Q = (D <= 2) ? 16 : (D == 3 ? 8 : (D == 4 ? 16 : 32));   // points per item
+  static constexpr int NG = kBlock / L;                            // groups per workgroup
+};
+constexpr int kMaxTileCells = 256;
+constexpr int kMaxItems = 2048 / 8 + kMaxTileCells;   // ppb <= 2048 points, Q >= 8
+
+// Polynomial coefficients (t^0..t^3) of the cubic piece b_a on one interval.
+template <typename T>
+__device__ __forceinline__ void piece_coeffs(int a, T& c0, T& c1, T& c2, T& c3) {
+  if (a == 0) { c0 = T(1.0 / 6.0); c1 = T(-0.5); c2 = T(0.5); c3 = T(-1.0 / 6.0); }
+  else if (a == 1) { c0 = T(2.0 / 3.0); c1 = T(0.0); c2 = T(-1.0); c3 = T(0.5); }
+  else if (a == 2) { c0 = T(1.0 / 6.0); c1 = T(0.5); c2 = T(0.5); c3 = T(-0.5); }
+  else { c0 = T(0.0); c1 = T(0.0); c2 = T(0.0); c3 = T(1.0 / 6.0); }
+}
+
+template <typename T, int L>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <int D, typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
+  using GP = Group<D>;
+  constexpr int L = GP::L;
+  constexpr int V = GP::V;
+  constexpr int Q = GP::Q;
+  constexpr int NLEAD = (D >= 3) ? D - 2 : 0;       // dimensions owned by the lane index
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int it_cell[kMaxItems];
+  __shared__ int it_lo[kMaxItems];
+  __shared__ int it_cnt[kMaxItems];
+  __shared__ int scan_sh[kBlock / 64];
+
+  T* lc = reinterpret_cast<T*>(smem_raw);
+  const int Tg = 1 << a.tb;
+  const int P = Tg + kDeg;
+  int patch = 1;
+#pragma unroll
+  for (int p = 0; p < D; ++p) patch *= P;
+  T* lacc = (MODE == kApply) ? lc + patch : lc;
+
+  int st[D];
+  st[D - 1] = 1;
+#pragma unroll
+  for (int p = D - 2; p >= 0; --p) st[p] = st[p + 1] * P;
+
+  const int Jg = (1 << a.g) + kDeg;
+  const int sh = a.G - a.g;                       // finest -> level g shift
+  const uint32_t maskN = (1u << a.G) - 1u;
+  const uint32_t maskSh = (1u << sh) - 1u;
+  const T scale = T(1.0) / T(double(1u << sh));   // exact power of two
+  const int S = D * (sh + a.tb);                  // finest Morton key -> tile index
+  const int cells_in_tile = 1 << (D * a.tb);
+  const T* tfrac = reinterpret_cast<const T*>(a.tfrac);
+  const T* cin = reinterpret_cast<const T*>(a.c);
+  T* out = reinterpret_cast<T*>(a.out);
+
+  // the lane's place in its group and its fixed leading multi-index
+  const int grp = threadIdx.x / L;
+  const int lig = threadIdx.x % L;
+  T hc[NLEAD > 0 ? NLEAD : 1][4];
+  int lead_off = 0;
+#pragma unroll
+  for (int q = 0; q < NLEAD; ++q) {
+    const int aq = (lig >> (2 * (NLEAD - 1 - q))) & 3;
+    piece_coeffs<T>(aq, hc[q][0], hc[q][1], hc[q][2], hc[q][3]);
+    lead_off += aq * st[q];
+  }
+
+  int64_t pos = int64_t(blockIdx.x) * a.ppb;
+  const int64_t end = min(a.n, pos + int64_t(a.ppb));
+  while (pos < end) {
+    const uint32_t tile = a.mkey[pos] >> S;
+    const int64_t seg_end = min(end, int64_t(a.off[size_t(tile + 1) << S]));
+    if (seg_end <= pos) break;   // offsets are monotone with off[N^D] = n; never taken
+    int org[D];
+    morton_decode<D>(tile, a.g - a.tb, org);
+#pragma unroll
+    for (int p = 0; p < D; ++p) org[p] *= Tg;
+
+    // per-cell point ranges of this segment, cut into items of <= Q points;
+    // thread j owns cell j of the tile (cells_in_tile <= kBlock)
+    int nch = 0, cnt = 0, lo_rel = 0;
+    if (int(threadIdx.x) < cells_in_tile) {
+      const size_t gc = (size_t(tile) << (D * a.tb)) + size_t(threadIdx.x);
+      int64_t lo = a.off[gc << (D * sh)], hi = a.off[(gc + 1) << (D * sh)];
+      lo = max(lo, pos);
+      hi = min(hi, seg_end);
+      cnt = hi > lo ? int(hi - lo) : 0;
+      lo_rel = int(lo - pos);
+      nch = (cnt + Q - 1) / Q;
+    }
+    // stage the coefficient patch, clear the accumulator
+    for (int e = threadIdx.x; e < patch; e += kBlock) {
+      if constexpr (MODE == kApply) {
+        int rem = e;
+        int64_t gidx = 0;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+          const int l = rem / st[p];
+          rem -= l * st[p];
+          gidx = gidx * Jg + (org[p] + l);
+        }
+        lc[e] = cin[gidx];
+      }
+      lacc[e] = T(0);
+    }
+    int n_items_all;
+    const int first = block_exclusive_scan(nch, scan_sh, &n_items_all);
+    // first + k < ppb / Q + kMaxTileCells <= kMaxItems (the host caps ppb at 2048)
+    for (int k = 0; k < nch && first + k < kMaxItems; ++k) {
+      it_cell[first + k] = int(threadIdx.x);
+      it_lo[first + k] = lo_rel + k * Q;
+      it_cnt[first + k] = min(Q, cnt - k * Q);
+    }
+    __syncthreads();
+    const int n_items = min(n_items_all, kMaxItems);
+
+    for (int it = grp; it < n_items; it += GP::NG) {
+      const int j = it_cell[it];
+      int cl[D];
+      morton_decode<D>(uint32_t(j), a.tb, cl);
+      int base = lead_off;
+#pragma unroll
+      for (int p = 0; p < D; ++p) base += cl[p] * st[p];
+      int sa = 0;
+      if constexpr (D >= 2) sa = st[D - 2];
+      T cv[V], acc[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int off = (D == 1) ? v : ((v >> 2) * sa + (v & 3));
+        if constexpr (MODE == kApply) cv[v] = lc[base + off];
+        acc[v] = T(0);
+      }
+      const int64_t i0 = pos + it_lo[it];
+      const int64_t i1 = i0 + it_cnt[it];
+      for (int64_t i = i0; i < i1; ++i) {
+        const uint32_t cf = a.cell[i];
+        T tt[D];
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+          const uint32_t cfp = (cf >> (a.G * (D - 1 - p))) & maskN;
+          tt[p] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + size_t(i)]) * scale;
+        }
+        // the lane's factor of the leading dimensions
+        T w = T(1);
+#pragma unroll
+        for (int q = 0; q < NLEAD; ++q) w *= ((hc[q][3] * tt[q] + hc[q][2]) * tt[q] + hc[q][1]) * tt[q] + hc[q][0];
+        T bm1[4], bm2[4];
+        cubic_basis(tt[D - 1], bm1);
+        if constexpr (D >= 2) cubic_basis(tt[D - 2], bm2);
+        T s;
+        if constexpr (MODE == kApply) {
+          T tl = T(0);
+          if constexpr (D == 1) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) tl += bm1[b] * cv[b];
+          } else {
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+              T r = T(0);
+#pragma unroll
+              for (int b = 0; b < 4; ++b) r += bm1[b] * cv[aa * 4 + b];
+              tl += bm2[aa] * r;
+            }
+          }
+          s = group_sum<T, L>(w * tl);
+        } else if constexpr (MODE == kRhs) {
+          s = T(a.y[i]);
+        } else {
+          s = T(1);
+        }
+        if constexpr (MODE == kDiag) {
+          const T u = s * w * w;
+          if constexpr (D == 1) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[b] += u * bm1[b] * bm1[b];
+          } else {
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+              const T ua = u * bm2[aa] * bm2[aa];
+#pragma unroll
+              for (int b = 0; b < 4; ++b) acc[aa * 4 + b] += ua * bm1[b] * bm1[b];
+            }
+          }
+        } else {
+          const T u = s * w;
+          if constexpr (D == 1) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[b] += u * bm1[b];
+          } else {
+#pragma unroll
+            for (int aa = 0; aa < 4; ++aa) {
+              const T ua = u * bm2[aa];
+#pragma unroll
+              for (int b = 0; b < 4; ++b) acc[aa * 4 + b] += ua * bm1[b];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int off = (D == 1) ? v : ((v >> 2) * sa + (v & 3));
+        atomicAdd(&lacc[base + off], acc[v]);
+      }
+    }
+    __syncthreads();
+
+    for (int e = threadIdx.x; e < patch; e += kBlock) {
+      const T v = lacc[e];
+      if (v != T(0)) {
+        int rem = e;
+        int64_t gidx = 0;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+          const int l = rem / st[p];
+          rem -= l * st[p];
+          gidx = gidx * Jg + (org[p] + l);
+        }
+        atomicAdd(&out[gidx], v);
+      }
+    }
+    __syncthreads();
+    pos = seg_end;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// lambda * Lambda_g c by the three-accumulator sum factorisation of
+// Lambda = sum_p (M x..x G2_p x..x M) + 2 sum_{p<q} (M x..G1_p..G1_q..x M):
+// after processing dimensions 0..p the tensors hold
+//   T0 = (M x..x M) c, T1 = sum of one G1 factor, T2 = Lambda restricted to the
+// processed dimensions; one pass applies along dimension p
+//   T2' = M T2 + G2 T0 + 2 G1 T1,  T1' = M T1 + G1 T0,  T0' = M T0.
+// `band` holds three J x 7 banded factors (M, G1, G2), row j column j+o-3.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lambda_pass(LambdaArgs<T> a) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= a.K) return;
+  const int64_t S = a.stride;
+  const int jp = int((k / S) % a.J);
+  const T* m = a.band + size_t(jp) * 7;
+  const T* g1 = a.band + size_t(a.J) * 7 + size_t(jp) * 7;
+  const T* g2 = a.band + size_t(2 * a.J) * 7 + size_t(jp) * 7;
+  T s0 = T(0), s1 = T(0), s2 = T(0);
+#pragma unroll
+  for (int o = -3; o <= 3; ++o) {
+    const int jj = jp + o;
+    if (jj < 0 || jj >= a.J) continue;
+    const int64_t idx = k + int64_t(o) * S;
+    const T v0 = a.in0[idx];
+    const T mm = m[o + 3], gg1 = g1[o + 3], gg2 = g2[o + 3];
+    if (a.first) {
+      s0 += mm * v0;
+      s1 += gg1 * v0;
+      s2 += gg2 * v0;
+    } else {
+      const T v1 = a.in1[idx], v2 = a.in2[idx];
+      s0 += mm * v0;
+      s1 += mm * v1 + gg1 * v0;
+      s2 += mm * v2 + gg2 * v0 + T(2) * gg1 * v1;
+    }
+  }
+  if (a.last) {
+    a.out[k] = a.lam * s2;
+  } else {
+    a.out0[k] = s0;
+    a.out1[k] = s1;
+    a.out2[k] = s2;
+  }
+}
+
+// lambda * diag(Lambda_g) from the diagonals of the 1D factors; `band` holds
+// [D][3][J][7] (each dimension has its own mesh width).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_lambda_diag(const double* band, int J, int64_t K,
+                                                        double lam, double* out) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  double md[D], g1d[D], g2d[D];
+  int64_t rem = k;
+#pragma unroll
+  for (int p = D - 1; p >= 0; --p) {
+    const int j = int(rem % J);
+    rem /= J;
+    const double* bp = band + size_t(p) * 3 * J * 7;   // dimension p's factors
+    md[p] = bp[size_t(j) * 7 + 3];
+    g1d[p] = bp[size_t(J) * 7 + size_t(j) * 7 + 3];
+    g2d[p] = bp[size_t(2 * J) * 7 + size_t(j) * 7 + 3];
+  }
+  double total = 0.0;
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    double t = g2d[p];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      if (q != p) t *= md[q];
+    total += t;
+  }
+#pragma unroll
+  for (int p = 0; p < D; ++p)
+#pragma unroll
+    for (int q = p + 1; q < D; ++q) {
+      double t = 2.0 * g1d[p] * g1d[q];
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+        if (r != p && r != q) t *= md[r];
+      total += t;
+    }
+  out[k] = lam * total;
+}
+
+// ---------------------------------------------------------------------------
+// Grid transfer, one dimension per pass (Alg. 2 with the 1D subdivision
+// matrix of eq. 2.5, 0-based I[i, j] = binom(4, i - 2j + 3) / 8):
+// prolongation expands dimension p from Jc to Jf = 2 Jc - 3, restriction
+// contracts it back with the transposed weights.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_pass(TransferArgs<T> a) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= a.Kout) return;
+  const int64_t inner = a.inner;
+  const int64_t ii = k % inner;
+  const int64_t rest = k / inner;
+  const int i = int(rest % a.Jf);
+  const int64_t outer = rest / a.Jf;
+  const int64_t ibase = outer * a.Jc * inner + ii;
+  T v;
+  const int mm = i >> 1;
+  if (i & 1) {
+    v = T(0.125) * a.in[ibase + int64_t(mm) * inner];
+    if (mm + 1 < a.Jc) v += T(0.75) * a.in[ibase + int64_t(mm + 1) * inner];
+    if (mm + 2 < a.Jc) v += T(0.125) * a.in[ibase + int64_t(mm + 2) * inner];
+  } else {
+    v = T(0.5) * a.in[ibase + int64_t(mm) * inner];
+    if (mm + 1 < a.Jc) v += T(0.5) * a.in[ibase + int64_t(mm + 1) * inner];
+  }
+  if (a.subtract) a.out[k] -= v;
+  else a.out[k] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_pass(TransferArgs<T> a) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= a.Kout) return;
+  const int64_t inner = a.inner;
+  const int64_t ii = k % inner;
+  const int64_t rest = k / inner;
+  const int j = int(rest % a.Jc);
+  const int64_t outer = rest / a.Jc;
+  const int64_t ibase = outer * a.Jf * inner + ii;
+  const T w[5] = {T(0.125), T(0.5), T(0.75), T(0.5), T(0.125)};
+  T v = T(0);
+#pragma unroll
+  for (int m = 0; m < 5; ++m) {
+    const int i = 2 * j - 3 + m;
+    if (i >= 0 && i < a.Jf) v += w[m] * a.in[ibase + int64_t(i) * inner];
+  }
+  a.out[k] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi smoother and residual epilogues (Alg. 6, Alg. 7).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) alpha[k] = wdinv[k] * b[k];
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi(T* alpha, const T* wdinv, const T* b, const T* Ax, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) alpha[k] += wdinv[k] * (b[k] - Ax[k]);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(T* r, const T* Ax, const T* b, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) r[k] = Ax[k] - b[k];
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernels. Reductions accumulate in FP64 whatever the input type and
+// are two-stage (per-block partials, then one block) so results do not depend
+// on scheduling.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+template <typename TX, typename TY>
+__global__ __launch_bounds__(kBlock) void k_dot_partial(const TX* x, const TY* y, int64_t K, double* partial) {
+  __shared__ double sh[kBlock / 64];
+  double v = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < K; k += int64_t(gridDim.x) * kBlock)
+    v += double(x[k]) * double(y[k]);
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, int nb, double* slot) {
+  __shared__ double sh[kBlock / 64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) v += partial[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) *slot = v;
+}
+
+// alpha += w p; r -= w v with w = (*num) / (*den) read on the device.
+template <typename TA, typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_step(TA* alpha, T* r, const T* p, const T* v, int64_t K,
+                                                    const double* num, const double* den) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  const double w = *num / *den;
+  alpha[k] = TA(double(alpha[k]) + w * double(p[k]));
+  r[k] = T(double(r[k]) - w * double(v[k]));
+}
+
+// p = z + beta p with beta = (*num) / (*den).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_p_update(T* p, const T* z, int64_t K, const double* num,
+                                                     const double* den) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  const double beta = *num / *den;
+  p[k] = T(double(z[k]) + beta * double(p[k]));
+}
+
+// y = s * x with conversion; s = scale * (*sden)^(-1/2) when sden is given.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_scale_copy(const TI* x, TO* y, int64_t K, double scale,
+                                                       const double* sden) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  double s = scale;
+  if (sden) s = s / sqrt(*sden);
+  y[k] = TO(s * double(x[k]));
+}
+
+// y += s * x (x converted to y's type), s as in k_scale_copy but multiplied.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_axpy_conv(const TI* x, TO* y, int64_t K, double scale,
+                                                      const double* smul) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  double s = scale;
+  if (smul) s = s * sqrt(*smul);
+  y[k] = TO(double(y[k]) + s * double(x[k]));
+}
+
+// Lanczos pieces: y = d .* x ; w = d .* x - beta_prev v_prev (beta from slot).
+__global__ __launch_bounds__(kBlock) void k_mul(const double* d, const double* x, double* y, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) y[k] = d[k] * x[k];
+}
+__global__ __launch_bounds__(kBlock) void k_lanczos_w(const double* d, const double* Ax, const double* vprev,
+                                                      double beta_prev, double* w, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) w[k] = d[k] * Ax[k] - beta_prev * vprev[k];
+}
+__global__ __launch_bounds__(kBlock) void k_axpy(double a, const double* x, double* y, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) y[k] += a * x[k];
+}
+__global__ __launch_bounds__(kBlock) void k_start_vector(double* u, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) {
+    const uint64_t h = (uint64_t(k) * 2654435761ull) & 0xffffffffull;
+    u[k] = double(h) / 4294967296.0 - 0.5;
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_rsqrt_vec(const double* D, double* out, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) out[k] = 1.0 / sqrt(D[k]);
+}
+__global__ __launch_bounds__(kBlock) void k_wdinv(const double* D, double omega, double* w64, float* w32,
+                                                  int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) {
+    const double v = omega / D[k];
+    w64[k] = v;
+    w32[k] = float(v);
+  }
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill(T* x, T v, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K) x[k] = v;
+}
+// Sets nonfinite/flag bits: 1 if any value is not finite.
+__global__ __launch_bounds__(kBlock) void k_check_finite(const double* x, int64_t K, int* flag) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k < K && !isfinite(x[k])) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Setup: bin every point into its finest knot cell (reading: c = min(floor(
+// (x - lo) / h), N - 1)), record the Morton key of the cell for the sort and
+// flag non-finite or out-of-box coordinates.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_bin(const double* x, int64_t n, BoxArgs box, uint32_t* key,
+                                                uint32_t* idx, int* flag) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n) return;
+  uint32_t k = 0;
+  int bad = 0;
+  const uint32_t N = 1u << box.G;
+  uint32_t c[D];
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    const double xv = x[size_t(i) * D + p];
+    if (!isfinite(xv)) { bad |= 2; c[p] = 0; continue; }
+    if (xv < box.lo[p] || xv > box.hi[p]) { bad |= 4; c[p] = 0; continue; }
+    const double u = (xv - box.lo[p]) * box.inv_h[p];
+    int64_t ci = int64_t(floor(u));
+    ci = ci < 0 ? 0 : (ci > int64_t(N) - 1 ? int64_t(N) - 1 : ci);
+    c[p] = uint32_t(ci);
+  }
+  for (int b = 0; b < box.G; ++b)
+#pragma unroll
+    for (int p = 0; p < D; ++p) k |= ((c[p] >> b) & 1u) << (b * D + (D - 1 - p));
+  key[i] = k;
+  idx[i] = uint32_t(i);
+  if (bad) atomicOr(flag, bad);
+}
+
+// Gather the sorted points into structure-of-arrays storage.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_place(const double* x, const double* y, const uint32_t* idx,
+                                                  int64_t n, BoxArgs box, double* t64, float* t32,
+                                                  uint32_t* cell, double* ys) {
+  const int64_t s = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (s >= n) return;
+  const int64_t i = idx[s];
+  const int64_t N = int64_t(1) << box.G;
+  uint32_t cf = 0;
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    const double u = (x[size_t(i) * D + p] - box.lo[p]) * box.inv_h[p];
+    int64_t ci = int64_t(floor(u));
+    ci = ci < 0 ? 0 : (ci > N - 1 ? N - 1 : ci);
+    double t = u - double(ci);
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    t64[size_t(p) * n + s] = t;
+    t32[size_t(p) * n + s] = float(t);
+    cf = cf * uint32_t(N) + uint32_t(ci);
+  }
+  cell[s] = cf;
+  ys[s] = y[i];
+}
+
+// off[c] = first sorted position whose key is >= c, c = 0..ncells.
+__global__ __launch_bounds__(kBlock) void k_offsets(const uint32_t* key, int64_t n, int64_t ncells,
+                                                    int32_t* off) {
+  const int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (c > ncells) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (int64_t(key[mid]) < c) lo = mid + 1; else hi = mid;
+  }
+  off[c] = int32_t(lo);
+}
+
+// ---------------------------------------------------------------------------
+// s(x) at query points (eq. 2.2): cell of each query on the finest grid,
+// 1D cubic values, tensor gather from global memory.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_eval(const double* alpha, const double* xq, int64_t m,
+                                                 BoxArgs box, double* yq) {
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= m) return;
+  const int N = 1 << box.G;
+  const int J = N + kDeg;
+  int st[D];
+  st[D - 1] = 1;
+#pragma unroll
+  for (int p = D - 2; p >= 0; --p) st[p] = st[p + 1] * J;
+  double B[D][4];
+  int base = 0;
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    const double u = (xq[size_t(i) * D + p] - box.lo[p]) * box.inv_h[p];
+    double fl = floor(u);
+    fl = fl < 0.0 ? 0.0 : (fl > double(N - 1) ? double(N - 1) : fl);
+    cubic_basis(u - fl, B[p]);
+    base += int(fl) * st[p];
+  }
+  yq[i] = patch_gather<D, double>(alpha, base, B, st);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse matrix A_1 (Sec. 3.2.4) from polynomial moments. On a level-1 cell
+// the tensor basis row is v_i = kron_p b(u_ip) with u = t - 1/2, so
+// sum_i v_i v_i' = sum_e M[e] kron_p C_{e_p}, M[e] = sum_i prod_p u_ip^e_p
+// (e in 0..6 per dimension) and C_e[a, a'] the u^e coefficient of b_a b_a'.
+//
+// Moments of the points of level-1 cell blockIdx.y, exponent tuples
+// (e_1..e_{D-1}) = blockIdx.x * kBlock + threadIdx.x with all seven e_0,
+// points of chunk blockIdx.z; accumulated with atomics (mom zeroed before).
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_moments(const double* t64, const uint32_t* cell,
+                                                    const int32_t* off, int64_t n, int G, int chunks,
+                                                    double* mom) {
+  constexpr int E = 7;
+  constexpr int TILE = 64;
+  __shared__ double pw[TILE][D][E];
+  int nrest = 1;
+#pragma unroll
+  for (int p = 1; p < D; ++p) nrest *= E;
+  const int cidx = blockIdx.y;
+  const int S = D * (G - 1);
+  const int64_t c0 = off[size_t(cidx) << S], c1 = off[size_t(cidx + 1) << S];
+  const int64_t len = c1 - c0;
+  const int64_t per = (len + chunks - 1) / chunks;
+  const int64_t b0 = c0 + int64_t(blockIdx.z) * per;
+  const int64_t b1 = min(c1, b0 + per);
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  int er[D];
+  {
+    int rem = r;
+#pragma unroll
+    for (int p = D - 1; p >= 1; --p) { er[p] = rem % E; rem /= E; }
+    er[0] = 0;
+  }
+  const int sh = G - 1;
+  const uint32_t maskN = (1u << G) - 1u, maskSh = (1u << sh) - 1u;
+  const double scale = 1.0 / double(1u << sh);
+  double acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0;
+  for (int64_t base = b0; base < b1; base += TILE) {
+    __syncthreads();
+    for (int w = threadIdx.x; w < TILE * D; w += kBlock) {
+      const int pt = w / D, p = w % D;
+      const int64_t i = base + pt;
+      double u = 0.0;
+      bool ok = i < b1;
+      if (ok) {
+        const uint32_t cf = cell[i];
+        const uint32_t cfp = (cf >> (G * (D - 1 - p))) & maskN;
+        u = (double(cfp & maskSh) + t64[size_t(p) * n + i]) * scale - 0.5;
+      }
+      double v = ok ? 1.0 : 0.0;
+      for (int e = 0; e < E; ++e) { pw[pt][p][e] = v; v *= u; }
+    }
+    __syncthreads();
+    if (r < nrest) {
+      const int cnt = int(min(int64_t(TILE), b1 - base));
+      for (int pt = 0; pt < cnt; ++pt) {
+        double prod = 1.0;
+#pragma unroll
+        for (int p = 1; p < D; ++p) prod *= pw[pt][p][er[p]];
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] += prod * pw[pt][0][e];
+      }
+    }
+  }
+  if (r < nrest && b0 < b1) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) atomicAdd(&mom[size_t(cidx) * (E * nrest) + size_t(e) * nrest + r], acc[e]);
+  }
+}
+
+// One contraction step: replace exponent e_p by the basis pair (a_p, a'_p).
+// in  [cells][16^p][7][R], out [cells][16^p][16][R], R = 7^(D-1-p).
+__global__ __launch_bounds__(kBlock) void k_contract(const double* in, double* out, const double* ctab,
+                                                     int64_t cellsA, int64_t R, int64_t total) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= total) return;
+  const int64_t er = k % R;
+  const int64_t rest = k / R;
+  const int pi = int(rest % 16);
+  const int64_t ca = rest / 16;   // (cell, previous pairs) combined index
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < 7; ++e) s += ctab[e * 16 + pi] * in[(ca * 7 + e) * R + er];
+  out[k] = s;
+}
+
+// A_1[k, k'] = sum over level-1 cells c of Gram_c[(k - c), (k' - c)]
+//            + lambda Lambda_1[k, k'].
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_assemble_a1(const double* gram, const double* band, double lam,
+                                                        double* A1) {
+  constexpr int J = 5;
+  int K1 = 1;
+#pragma unroll
+  for (int p = 0; p < D; ++p) K1 *= J;
+  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= int64_t(K1) * K1) return;
+  const int kr = int(t / K1), kc = int(t % K1);
+  int jr[D], jc[D];
+  {
+    int a = kr, b = kc;
+#pragma unroll
+    for (int p = D - 1; p >= 0; --p) { jr[p] = a % J; a /= J; jc[p] = b % J; b /= J; }
+  }
+  double s = 0.0;
+  for (int c = 0; c < (1 << D); ++c) {
+    bool ok = true;
+    int64_t pidx = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      const int cp = (c >> (D - 1 - p)) & 1;
+      const int ar = jr[p] - cp, ac = jc[p] - cp;
+      ok = ok && ar >= 0 && ar <= 3 && ac >= 0 && ac <= 3;
+      pidx = pidx * 16 + (ar * 4 + ac);
+    }
+    if (ok) s += gram[size_t(c) * (size_t(1) << (4 * D)) + pidx];
+  }
+  // Lambda_1 entry from the banded 1D factors (|j - l| <= 3 always holds for J = 5).
+  double lm = 0.0;
+  double mv[D], g1v[D], g2v[D];
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    const int o = jc[p] - jr[p] + 3;
+    const double* bp = band + p * 3 * J * 7;   // dimension p's factors
+    mv[p] = bp[jr[p] * 7 + o];
+    g1v[p] = bp[J * 7 + jr[p] * 7 + o];
+    g2v[p] = bp[2 * J * 7 + jr[p] * 7 + o];
+  }
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    double v = g2v[p];
+#pragma unroll
+    for (int q = 0; q < D; ++q)
+      if (q != p) v *= mv[q];
+    lm += v;
+  }
+#pragma unroll
+  for (int p = 0; p < D; ++p)
+#pragma unroll
+    for (int q = p + 1; q < D; ++q) {
+      double v = 2.0 * g1v[p] * g1v[q];
+#pragma unroll
+      for (int r = 0; r < D; ++r)
+        if (r != p && r != q) v *= mv[r];
+      lm += v;
+    }
+  A1[t] = s + lam * lm;
+}
+
+// In-place Gauss-Jordan inversion without pivoting (A_1 is SPD), step k:
+// save row k and column k, then update every entry from the saved copies.
+__global__ __launch_bounds__(kBlock) void k_gj_save(const double* A, int K, int k, double* row, double* col,
+                                                    double* piv) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < K) {
+    row[i] = A[size_t(k) * K + i];
+    col[i] = A[size_t(i) * K + k];
+  }
+  if (i == 0) piv[k] = A[size_t(k) * K + k];
+}
+__global__ __launch_bounds__(kBlock) void k_gj_update(double* A, int K, int k, const double* row,
+                                                      const double* col) {
+  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= int64_t(K) * K) return;
+  const int i = int(t / K), j = int(t % K);
+  const double p = row[k];
+  const double rj = (j == k) ? 1.0 : row[j];
+  if (i == k) {
+    A[t] = rj / p;
+  } else {
+    const double aij = (j == k) ? 0.0 : A[t];
+    A[t] = aij - col[i] * rj / p;
+  }
+}
+__global__ __launch_bounds__(kBlock) void k_symmetrize(double* A, int K) {
+  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= int64_t(K) * K) return;
+  const int i = int(t / K), j = int(t % K);
+  if (i < j) {
+    const double v = 0.5 * (A[t] + A[size_t(j) * K + i]);
+    A[t] = v;
+    A[size_t(j) * K + i] = v;
+  }
+}
+
+// out = base + s * A v for a dense K x K matrix, one wavefront per row, FP64
+// arithmetic whatever the I/O types (base may be null).
+template <typename TB, typename TV, typename TO>
+__global__ __launch_bounds__(kBlock) void k_gemv(const double* A, int K, const TB* base, double s, const TV* v,
+                                                 TO* out) {
+  const int row = (blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= K) return;
+  double acc = 0.0;
+  for (int j = lane; j < K; j += 64) acc += A[size_t(row) * K + j] * double(v[j]);
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) out[row] = TO((base ? double(base[row]) : 0.0) + s * acc);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+static inline unsigned blocks_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+template <int D, typename T, int MODE>
+static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
+  const int Tg = 1 << a.tb;
+  int patch = 1;
+  for (int p = 0; p < D; ++p) patch *= (Tg + kDeg);
+  const size_t lds = size_t(patch) * sizeof(T) * (MODE == kApply ? 2 : 1);
+  const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
+  if (grid == 0) return hipSuccess;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_data<D, T, MODE>), dim3(grid), dim3(kBlock), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename T, int MODE>
+static hipError_t launch_data_t(int D, const DataArgs& a, hipStream_t st) {
+  switch (D) {
+    case 1: return launch_data_d<1, T, MODE>(a, st);
+    case 2: return launch_data_d<2, T, MODE>(a, st);
+    case 3: return launch_data_d<3, T, MODE>(a, st);
+    case 4: return launch_data_d<4, T, MODE>(a, st);
+    case 5: return launch_data_d<5, T, MODE>(a, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_data(int D, bool fp32, int mode, const DataArgs& a, hipStream_t st) {
+  if (fp32) {
+    if (mode == kApply) return launch_data_t<float, kApply>(D, a, st);
+    return hipErrorInvalidValue;
+  }
+  if (mode == kApply) return launch_data_t<double, kApply>(D, a, st);
+  if (mode == kRhs) return launch_data_t<double, kRhs>(D, a, st);
+  if (mode == kDiag) return launch_data_t<double, kDiag>(D, a, st);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipStream_t st) {
+  if (a.K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lambda_pass<T>, dim3(blocks_for(a.K)), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_lambda_pass<double>(const LambdaArgs<double>&, hipStream_t);
+template hipError_t launch_lambda_pass<float>(const LambdaArgs<float>&, hipStream_t);
+
+hipError_t launch_lambda_diag(int D, const double* band, int J, int64_t K, double lam, double* out,
+                              hipStream_t st) {
+  const unsigned g = blocks_for(K);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_lambda_diag<1>, dim3(g), dim3(kBlock), 0, st, band, J, K, lam, out); break;
+    case 2: hipLaunchKernelGGL(k_lambda_diag<2>, dim3(g), dim3(kBlock), 0, st, band, J, K, lam, out); break;
+    case 3: hipLaunchKernelGGL(k_lambda_diag<3>, dim3(g), dim3(kBlock), 0, st, band, J, K, lam, out); break;
+    case 4: hipLaunchKernelGGL(k_lambda_diag<4>, dim3(g), dim3(kBlock), 0, st, band, J, K, lam, out); break;
+    case 5: hipLaunchKernelGGL(k_lambda_diag<5>, dim3(g), dim3(kBlock), 0, st, band, J, K, lam, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transfer(bool prolong, const TransferArgs<T>& a, hipStream_t st) {
+  if (a.Kout == 0) return hipSuccess;
+  if (prolong) hipLaunchKernelGGL(k_prolong_pass<T>, dim3(blocks_for(a.Kout)), dim3(kBlock), 0, st, a);
+  else hipLaunchKernelGGL(k_restrict_pass<T>, dim3(blocks_for(a.Kout)), dim3(kBlock), 0, st, a);
+  return hipGetLastError();
+}
+template hipError_t launch_transfer<double>(bool, const TransferArgs<double>&, hipStream_t);
+template hipError_t launch_transfer<float>(bool, const TransferArgs<float>&, hipStream_t);
+
+template <typename T>
+hipError_t launch_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_first<T>, dim3(blocks_for(K)), dim3(kBlock), 0, st, alpha, wdinv, b, K);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_jacobi(T* alpha, const T* wdinv, const T* b, const T* Ax, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi<T>, dim3(blocks_for(K)), dim3(kBlock), 0, st, alpha, wdinv, b, Ax, K);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_residual(T* r, const T* Ax, const T* b, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_residual<T>, dim3(blocks_for(K)), dim3(kBlock), 0, st, r, Ax, b, K);
+  return hipGetLastError();
+}
+template hipError_t launch_jacobi_first<double>(double*, const double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_jacobi_first<float>(float*, const float*, const float*, int64_t, hipStream_t);
+template hipError_t launch_jacobi<double>(double*, const double*, const double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_jacobi<float>(float*, const float*, const float*, const float*, int64_t, hipStream_t);
+template hipError_t launch_residual<double>(double*, const double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_residual<float>(float*, const float*, const float*, int64_t, hipStream_t);
+
+static inline unsigned reduce_blocks(int64_t K) {
+  int64_t b = (K + kBlock * 4 - 1) / (kBlock * 4);
+  if (b < 1) b = 1;
+  if (b > kMaxPartials) b = kMaxPartials;
+  return unsigned(b);
+}
+
+template <typename TX, typename TY>
+hipError_t launch_dot(const TX* x, const TY* y, int64_t K, double* partial, double* slot, hipStream_t st) {
+  const unsigned nb = reduce_blocks(K);
+  hipLaunchKernelGGL((k_dot_partial<TX, TY>), dim3(nb), dim3(kBlock), 0, st, x, y, K, partial);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, st, partial, int(nb), slot);
+  return hipGetLastError();
+}
+template hipError_t launch_dot<double, double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template hipError_t launch_dot<float, float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
+
+template <typename TA, typename T>
+hipError_t launch_cg_step(TA* alpha, T* r, const T* p, const T* v, int64_t K, const double* num,
+                          const double* den, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_step<TA, T>), dim3(blocks_for(K)), dim3(kBlock), 0, st, alpha, r, p, v, K, num, den);
+  return hipGetLastError();
+}
+template hipError_t launch_cg_step<double, double>(double*, double*, const double*, const double*, int64_t,
+                                                   const double*, const double*, hipStream_t);
+template hipError_t launch_cg_step<float, float>(float*, float*, const float*, const float*, int64_t,
+                                                 const double*, const double*, hipStream_t);
+
+template <typename T>
+hipError_t launch_p_update(T* p, const T* z, int64_t K, const double* num, const double* den, hipStream_t st) {
+  hipLaunchKernelGGL(k_p_update<T>, dim3(blocks_for(K)), dim3(kBlock), 0, st, p, z, K, num, den);
+  return hipGetLastError();
+}
+template hipError_t launch_p_update<double>(double*, const double*, int64_t, const double*, const double*, hipStream_t);
+template hipError_t launch_p_update<float>(float*, const float*, int64_t, const double*, const double*, hipStream_t);
+
+template <typename TI, typename TO>
+hipError_t launch_scale_copy(const TI* x, TO* y, int64_t K, double scale, const double* sden, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_copy<TI, TO>), dim3(blocks_for(K)), dim3(kBlock), 0, st, x, y, K, scale, sden);
+  return hipGetLastError();
+}
+template hipError_t launch_scale_copy<double, float>(const double*, float*, int64_t, double, const double*, hipStream_t);
+template hipError_t launch_scale_copy<float, double>(const float*, double*, int64_t, double, const double*, hipStream_t);
+template hipError_t launch_scale_copy<double, double>(const double*, double*, int64_t, double, const double*, hipStream_t);
+template hipError_t launch_scale_copy<float, float>(const float*, float*, int64_t, double, const double*, hipStream_t);
+
+template <typename TI, typename TO>
+hipError_t launch_axpy_conv(const TI* x, TO* y, int64_t K, double scale, const double* smul, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy_conv<TI, TO>), dim3(blocks_for(K)), dim3(kBlock), 0, st, x, y, K, scale, smul);
+  return hipGetLastError();
+}
+template hipError_t launch_axpy_conv<float, double>(const float*, double*, int64_t, double, const double*, hipStream_t);
+
+hipError_t launch_mul(const double* d, const double* x, double* y, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_mul, dim3(blocks_for(K)), dim3(kBlock), 0, st, d, x, y, K);
+  return hipGetLastError();
+}
+hipError_t launch_lanczos_w(const double* d, const double* Ax, const double* vprev, double beta_prev, double* w,
+                            int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_lanczos_w, dim3(blocks_for(K)), dim3(kBlock), 0, st, d, Ax, vprev, beta_prev, w, K);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double a, const double* x, double* y, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(K)), dim3(kBlock), 0, st, a, x, y, K);
+  return hipGetLastError();
+}
+hipError_t launch_start_vector(double* u, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_start_vector, dim3(blocks_for(K)), dim3(kBlock), 0, st, u, K);
+  return hipGetLastError();
+}
+hipError_t launch_rsqrt_vec(const double* D, double* out, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_rsqrt_vec, dim3(blocks_for(K)), dim3(kBlock), 0, st, D, out, K);
+  return hipGetLastError();
+}
+hipError_t launch_wdinv(const double* D, double omega, double* w64, float* w32, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_wdinv, dim3(blocks_for(K)), dim3(kBlock), 0, st, D, omega, w64, w32, K);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_fill(T* x, T v, int64_t K, hipStream_t st) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<T>, dim3(blocks_for(K)), dim3(kBlock), 0, st, x, v, K);
+  return hipGetLastError();
+}
+template hipError_t launch_fill<double>(double*, double, int64_t, hipStream_t);
+template hipError_t launch_fill<float>(float*, float, int64_t, hipStream_t);
+template hipError_t launch_fill<int>(int*, int, int64_t, hipStream_t);
+
+hipError_t launch_check_finite(const double* x, int64_t K, int* flag, hipStream_t st) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(K)), dim3(kBlock), 0, st, x, K, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(int D, const double* x, int64_t n, const BoxArgs& box, uint32_t* key, uint32_t* idx,
+                      int* flag, hipStream_t st) {
+  const unsigned g = blocks_for(n);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_bin<1>, dim3(g), dim3(kBlock), 0, st, x, n, box, key, idx, flag); break;
+    case 2: hipLaunchKernelGGL(k_bin<2>, dim3(g), dim3(kBlock), 0, st, x, n, box, key, idx, flag); break;
+    case 3: hipLaunchKernelGGL(k_bin<3>, dim3(g), dim3(kBlock), 0, st, x, n, box, key, idx, flag); break;
+    case 4: hipLaunchKernelGGL(k_bin<4>, dim3(g), dim3(kBlock), 0, st, x, n, box, key, idx, flag); break;
+    case 5: hipLaunchKernelGGL(k_bin<5>, dim3(g), dim3(kBlock), 0, st, x, n, box, key, idx, flag); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_place(int D, const double* x, const double* y, const uint32_t* idx, int64_t n,
+                        const BoxArgs& box, double* t64, float* t32, uint32_t* cell, double* ys, hipStream_t st) {
+  const unsigned g = blocks_for(n);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_place<1>, dim3(g), dim3(kBlock), 0, st, x, y, idx, n, box, t64, t32, cell, ys); break;
+    case 2: hipLaunchKernelGGL(k_place<2>, dim3(g), dim3(kBlock), 0, st, x, y, idx, n, box, t64, t32, cell, ys); break;
+    case 3: hipLaunchKernelGGL(k_place<3>, dim3(g), dim3(kBlock), 0, st, x, y, idx, n, box, t64, t32, cell, ys); break;
+    case 4: hipLaunchKernelGGL(k_place<4>, dim3(g), dim3(kBlock), 0, st, x, y, idx, n, box, t64, t32, cell, ys); break;
+    case 5: hipLaunchKernelGGL(k_place<5>, dim3(g), dim3(kBlock), 0, st, x, y, idx, n, box, t64, t32, cell, ys); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_offsets(const uint32_t* key, int64_t n, int64_t ncells, int32_t* off, hipStream_t st) {
+  hipLaunchKernelGGL(k_offsets, dim3(blocks_for(ncells + 1)), dim3(kBlock), 0, st, key, n, ncells, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int D, const double* alpha, const double* xq, int64_t m, const BoxArgs& box, double* yq,
+                       hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  const unsigned g = blocks_for(m);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_eval<1>, dim3(g), dim3(kBlock), 0, st, alpha, xq, m, box, yq); break;
+    case 2: hipLaunchKernelGGL(k_eval<2>, dim3(g), dim3(kBlock), 0, st, alpha, xq, m, box, yq); break;
+    case 3: hipLaunchKernelGGL(k_eval<3>, dim3(g), dim3(kBlock), 0, st, alpha, xq, m, box, yq); break;
+    case 4: hipLaunchKernelGGL(k_eval<4>, dim3(g), dim3(kBlock), 0, st, alpha, xq, m, box, yq); break;
+    case 5: hipLaunchKernelGGL(k_eval<5>, dim3(g), dim3(kBlock), 0, st, alpha, xq, m, box, yq); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n, int G,
+                          int chunks, double* mom, hipStream_t st) {
+  int nrest = 1;
+  for (int p = 1; p < D; ++p) nrest *= 7;
+  const dim3 grid(unsigned((nrest + kBlock - 1) / kBlock), 1u << D, unsigned(chunks));
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_moments<1>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
+    case 2: hipLaunchKernelGGL(k_moments<2>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
+    case 3: hipLaunchKernelGGL(k_moments<3>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
+    case 4: hipLaunchKernelGGL(k_moments<4>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
+    case 5: hipLaunchKernelGGL(k_moments<5>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(const double* in, double* out, const double* ctab, int64_t cellsA, int64_t R,
+                           hipStream_t st) {
+  const int64_t total = cellsA * 16 * R;
+  hipLaunchKernelGGL(k_contract, dim3(blocks_for(total)), dim3(kBlock), 0, st, in, out, ctab, cellsA, R, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_a1(int D, const double* gram, const double* band, double lam, double* A1, int K1,
+                              hipStream_t st) {
+  const unsigned g = blocks_for(int64_t(K1) * K1);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_assemble_a1<1>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
+    case 2: hipLaunchKernelGGL(k_assemble_a1<2>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
+    case 3: hipLaunchKernelGGL(k_assemble_a1<3>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
+    case 4: hipLaunchKernelGGL(k_assemble_a1<4>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
+    case 5: hipLaunchKernelGGL(k_assemble_a1<5>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gj_step(double* A, int K, int k, double* row, double* col, double* piv, hipStream_t st) {
+  hipLaunchKernelGGL(k_gj_save, dim3(blocks_for(K)), dim3(kBlock), 0, st, A, K, k, row, col, piv);
+  hipLaunchKernelGGL(k_gj_update, dim3(blocks_for(int64_t(K) * K)), dim3(kBlock), 0, st, A, K, k, row, col);
+  return hipGetLastError();
+}
+hipError_t launch_symmetrize(double* A, int K, hipStream_t st) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(blocks_for(int64_t(K) * K)), dim3(kBlock), 0, st, A, K);
+  return hipGetLastError();
+}
+
+template <typename TB, typename TV, typename TO>
+hipError_t launch_gemv(const double* A, int K, const TB* base, double s, const TV* v, TO* out, hipStream_t st) {
+  const unsigned g = unsigned((int64_t(K) * 64 + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_gemv<TB, TV, TO>), dim3(g), dim3(kBlock), 0, st, A, K, base, s, v, out);
+  return hipGetLastError();
+}
+template hipError_t launch_gemv<double, double, double>(const double*, int, const double*, double, const double*,
+                                                        double*, hipStream_t);
+template hipError_t launch_gemv<double, float, double>(const double*, int, const double*, double, const float*,
+                                                       double*, hipStream_t);
+template hipError_t launch_gemv<float, double, double>(const double*, int, const float*, double, const double*,
+                                                       double*, hipStream_t);
+template hipError_t launch_gemv<double, double, float>(const double*, int, const double*, double, const double*,
+                                                       float*, hipStream_t);
+
+}  // namespace tsmg

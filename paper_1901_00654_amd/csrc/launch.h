@@ -1,0 +1,96 @@
+// Host-side launchers of the tsmg kernels (defined in kernels.hip).
+#pragma once
+#include "common.h"
+
+namespace tsmg {
+
+constexpr int kMaxPartials = 1024;   // partial sums per reduction
+
+struct BoxArgs {
+  double lo[kMaxDim];
+  double hi[kMaxDim];
+  double inv_h[kMaxDim];   // N / (hi - lo)
+  int G;                   // N = 2^G intervals per dimension
+};
+
+template <typename T>
+struct LambdaArgs {
+  const T* in0; const T* in1; const T* in2;   // T0, T1, T2 (in1/in2 unused when first)
+  T* out0; T* out1; T* out2;                  // next T0, T1, T2 (unused when last)
+  T* out;                                     // lambda * T2 (last pass only)
+  const T* band;                              // [3][J][7]: M, G1, G2
+  int64_t K;                                  // J^D
+  int64_t stride;                             // J^(D-1-p)
+  int J;
+  int first, last;
+  T lam;
+};
+
+template <typename T>
+struct TransferArgs {
+  const T* in;
+  T* out;
+  int64_t Kout;     // output length
+  int64_t inner;    // product of the sizes of the dimensions after p
+  int Jc, Jf;       // coarse / fine length of dimension p
+  int subtract;     // prolongation only: out -= value instead of out = value
+};
+
+hipError_t launch_data(int D, bool fp32, int mode, const DataArgs& a, hipStream_t st);
+template <typename T> hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipStream_t st);
+hipError_t launch_lambda_diag(int D, const double* band, int J, int64_t K, double lam, double* out,
+                              hipStream_t st);
+template <typename T> hipError_t launch_transfer(bool prolong, const TransferArgs<T>& a, hipStream_t st);
+
+template <typename T> hipError_t launch_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K, hipStream_t st);
+template <typename T> hipError_t launch_jacobi(T* alpha, const T* wdinv, const T* b, const T* Ax, int64_t K,
+                                               hipStream_t st);
+template <typename T> hipError_t launch_residual(T* r, const T* Ax, const T* b, int64_t K, hipStream_t st);
+
+template <typename TX, typename TY>
+hipError_t launch_dot(const TX* x, const TY* y, int64_t K, double* partial, double* slot, hipStream_t st);
+template <typename TA, typename T>
+hipError_t launch_cg_step(TA* alpha, T* r, const T* p, const T* v, int64_t K, const double* num,
+                          const double* den, hipStream_t st);
+template <typename T>
+hipError_t launch_p_update(T* p, const T* z, int64_t K, const double* num, const double* den, hipStream_t st);
+template <typename TI, typename TO>
+hipError_t launch_scale_copy(const TI* x, TO* y, int64_t K, double scale, const double* sden, hipStream_t st);
+template <typename TI, typename TO>
+hipError_t launch_axpy_conv(const TI* x, TO* y, int64_t K, double scale, const double* smul, hipStream_t st);
+
+hipError_t launch_mul(const double* d, const double* x, double* y, int64_t K, hipStream_t st);
+hipError_t launch_lanczos_w(const double* d, const double* Ax, const double* vprev, double beta_prev, double* w,
+                            int64_t K, hipStream_t st);
+hipError_t launch_axpy(double a, const double* x, double* y, int64_t K, hipStream_t st);
+hipError_t launch_start_vector(double* u, int64_t K, hipStream_t st);
+hipError_t launch_rsqrt_vec(const double* D, double* out, int64_t K, hipStream_t st);
+hipError_t launch_wdinv(const double* D, double omega, double* w64, float* w32, int64_t K, hipStream_t st);
+template <typename T> hipError_t launch_fill(T* x, T v, int64_t K, hipStream_t st);
+hipError_t launch_check_finite(const double* x, int64_t K, int* flag, hipStream_t st);
+
+hipError_t launch_bin(int D, const double* x, int64_t n, const BoxArgs& box, uint32_t* key, uint32_t* idx,
+                      int* flag, hipStream_t st);
+hipError_t launch_place(int D, const double* x, const double* y, const uint32_t* idx, int64_t n,
+                        const BoxArgs& box, double* t64, float* t32, uint32_t* cell, double* ys, hipStream_t st);
+hipError_t launch_offsets(const uint32_t* key, int64_t n, int64_t ncells, int32_t* off, hipStream_t st);
+hipError_t launch_eval(int D, const double* alpha, const double* xq, int64_t m, const BoxArgs& box, double* yq,
+                       hipStream_t st);
+
+hipError_t launch_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n, int G,
+                          int chunks, double* mom, hipStream_t st);
+hipError_t launch_contract(const double* in, double* out, const double* ctab, int64_t cellsA, int64_t R,
+                           hipStream_t st);
+hipError_t launch_assemble_a1(int D, const double* gram, const double* band, double lam, double* A1, int K1,
+                              hipStream_t st);
+hipError_t launch_gj_step(double* A, int K, int k, double* row, double* col, double* piv, hipStream_t st);
+hipError_t launch_symmetrize(double* A, int K, hipStream_t st);
+// out = base + s * A v (dense K x K, FP64 arithmetic); base may be null.
+template <typename TB, typename TV, typename TO>
+hipError_t launch_gemv(const double* A, int K, const TB* base, double s, const TV* v, TO* out, hipStream_t st);
+
+// Radix sort of (key, index) pairs on the low `bits` bits (sort.hip).
+hipError_t sort_pairs(uint32_t* key_in, uint32_t* key_out, uint32_t* val_in, uint32_t* val_out, int64_t n,
+                      int bits, void* tmp, size_t* tmp_bytes, hipStream_t st);
+
+}  // namespace tsmg

@@ -1,0 +1,677 @@
+// Host side of tsmg: problem setup, the level hierarchy, the V-cycle (Alg. 7),
+// PCG (Alg. 8), the mixed-precision refinement loop and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tsmg.h"
+#include "launch.h"
+#include "problem.h"
+
+namespace tsmg {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& m) { g_last_error = m; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return;
+  if (e == hipErrorOutOfMemory) throw Error{TS_ENOMEM, std::string(what) + ": out of device memory"};
+  throw Error{TS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+// ---------------------------------------------------------------------------
+// 1D Gram matrices of the cubic B-splines on [lo, hi] with N uniform
+// intervals (Sec. 2.4): Psi_r[j, l] = int D^r B_j D^r B_l over the box.
+// Each interval contributes the same 4x4 block (the four pieces alive there,
+// as polynomials in t = (x - lo)/h - c), integrated exactly in t; the chain
+// rule gives the factor h^(1 - 2r). Stored banded: band[j][o] = Psi[j][j+o-3].
+static const double kPiece[4][4] = {
+    // coefficients of t^0..t^3 of the pieces, times 6
+    {1.0, -3.0, 3.0, -1.0},
+    {4.0, 0.0, -6.0, 3.0},
+    {1.0, 3.0, 3.0, -3.0},
+    {0.0, 0.0, 0.0, 1.0},
+};
+
+static void piece_deriv(int a, int r, double out[4]) {
+  double c[4];
+  for (int i = 0; i < 4; ++i) c[i] = kPiece[a][i] / 6.0;
+  for (int k = 0; k < r; ++k) {
+    for (int i = 0; i < 3; ++i) c[i] = c[i + 1] * double(i + 1);
+    c[3] = 0.0;
+  }
+  for (int i = 0; i < 4; ++i) out[i] = c[i];
+}
+
+void gram_band(double lo, double hi, int N, std::vector<double>& band /* [3][J][7] */) {
+  const int J = N + kDeg;
+  const double h = (hi - lo) / N;
+  band.assign(size_t(3) * J * 7, 0.0);
+  for (int r = 0; r < 3; ++r) {
+    double loc[4][4];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        double pa[4], pb[4];
+        piece_deriv(a, r, pa);
+        piece_deriv(b, r, pb);
+        double s = 0.0;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) s += pa[i] * pb[j] / double(i + j + 1);
+        loc[a][b] = s * std::pow(h, 1.0 - 2.0 * r);
+      }
+    for (int c = 0; c < N; ++c)
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) band[(size_t(r) * J + (c + a)) * 7 + (b - a + 3)] += loc[a][b];
+  }
+}
+
+// u^e coefficient (e = 0..6) of b_a(u + 1/2) b_a'(u + 1/2), pair index a*4+a'.
+void pair_table(std::vector<double>& ctab /* [7][16] */) {
+  ctab.assign(7 * 16, 0.0);
+  double shifted[4][4];
+  for (int a = 0; a < 4; ++a) {
+    for (int k = 0; k < 4; ++k) shifted[a][k] = 0.0;
+    // t^i = (u + 1/2)^i = sum_k binom(i, k) u^k (1/2)^(i-k)
+    for (int i = 0; i < 4; ++i) {
+      const double ci = kPiece[a][i] / 6.0;
+      double binom = 1.0;
+      for (int k = 0; k <= i; ++k) {
+        shifted[a][k] += ci * binom * std::pow(0.5, i - k);
+        binom = binom * double(i - k) / double(k + 1);
+      }
+    }
+  }
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) ctab[(i + j) * 16 + a * 4 + b] += shifted[a][i] * shifted[b][j];
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (alpha, beta) by bisection
+// on the Sturm count.
+double tridiag_max_eig(const std::vector<double>& al, const std::vector<double>& be) {
+  const int m = int(al.size());
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(be[i]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < m; ++i) {
+      const double b2 = (i > 0) ? be[i - 1] * be[i - 1] : 0.0;
+      q = al[i] - x - (i > 0 ? b2 / q : 0.0);
+      if (q == 0.0) q = -1e-300;
+      if (q < 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= m) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------------------
+// Operator pieces.
+template <typename T> static T* lvl_a(Level& L);
+template <> double* lvl_a<double>(Level& L) { return L.a64.p; }
+template <> float* lvl_a<float>(Level& L) { return L.a32.p; }
+template <typename T> static T* lvl_b(Level& L);
+template <> double* lvl_b<double>(Level& L) { return L.b64.p; }
+template <> float* lvl_b<float>(Level& L) { return L.b32.p; }
+template <typename T> static T* lvl_t(Level& L);
+template <> double* lvl_t<double>(Level& L) { return L.t64.p; }
+template <> float* lvl_t<float>(Level& L) { return L.t32.p; }
+template <typename T> static const T* lvl_w(Level& L);
+template <> const double* lvl_w<double>(Level& L) { return L.wdinv64.p; }
+template <> const float* lvl_w<float>(Level& L) { return L.wdinv32.p; }
+template <typename T> static const T* lvl_band(Level& L);
+template <> const double* lvl_band<double>(Level& L) { return L.band64.p; }
+template <> const float* lvl_band<float>(Level& L) { return L.band32.p; }
+template <typename T> static T* prob_lamS(Problem* P);
+template <> double* prob_lamS<double>(Problem* P) { return P->lamS64.p; }
+template <> float* prob_lamS<float>(Problem* P) { return P->lamS32.p; }
+template <typename T> static T* prob_xfer(Problem* P);
+template <> double* prob_xfer<double>(Problem* P) { return P->xfer64.p; }
+template <> float* prob_xfer<float>(Problem* P) { return P->xfer32.p; }
+
+// out = lambda Lambda_g c: D banded passes (the three-accumulator recursion).
+template <typename T>
+static void lambda_apply(Problem* P, int g, const T* c, T* out) {
+  Level& L = P->lev[g];
+  const int D = P->d;
+  const int64_t K = L.K;
+  T* S = prob_lamS<T>(P);
+  T* bufA = S;
+  T* bufB = S + 3 * P->lev[P->G].K;
+  const T* in0 = c;
+  const T* in1 = nullptr;
+  const T* in2 = nullptr;
+  int64_t stride = K;
+  for (int p = 0; p < D; ++p) {
+    stride /= L.J;
+    LambdaArgs<T> a{};
+    a.in0 = in0; a.in1 = in1; a.in2 = in2;
+    a.band = lvl_band<T>(L) + size_t(p) * 3 * L.J * 7;
+    a.K = K; a.stride = stride; a.J = L.J;
+    a.first = (p == 0); a.last = (p == D - 1);
+    a.lam = T(P->lam);
+    T* o = (p % 2 == 0) ? bufA : bufB;
+    a.out0 = o; a.out1 = o + K; a.out2 = o + 2 * K;
+    a.out = out;
+    hip_check(launch_lambda_pass<T>(a, P->stream), "lambda pass");
+    in0 = a.out0; in1 = a.out1; in2 = a.out2;
+  }
+}
+
+static DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out) {
+  Level& L = P->lev[g];
+  DataArgs a{};
+  a.tfrac = fp32 ? static_cast<const void*>(P->t32.p) : static_cast<const void*>(P->t64.p);
+  a.cell = P->cell.p;
+  a.mkey = P->mkey.p;
+  a.y = P->ys.p;
+  a.off = P->off.p;
+  a.c = c;
+  a.out = out;
+  a.n = P->n;
+  a.G = P->G;
+  a.g = g;
+  a.tb = L.tb;
+  a.ppb = P->ppb;
+  return a;
+}
+
+// out = A_g c (Sec. 2.4): Lambda passes write out, the point pass adds Phi'Phi c.
+template <typename T>
+void apply_op(Problem* P, int g, const T* c, T* out) {
+  lambda_apply<T>(P, g, c, out);
+  const bool fp32 = sizeof(T) == 4;
+  hip_check(launch_data(P->d, fp32, kApply, data_args(P, g, fp32, c, out), P->stream), "data pass");
+  P->applies++;
+}
+template void apply_op<double>(Problem*, int, const double*, double*);
+template void apply_op<float>(Problem*, int, const float*, float*);
+
+// out (level g) = I e (level g-1), or out -= I e when subtract is set.
+template <typename T>
+void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract) {
+  const int D = P->d;
+  const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
+  T* X = prob_xfer<T>(P);
+  T* bufs[2] = {X, X + P->lev[P->G].K};
+  const T* in = e;
+  for (int p = 0; p < D; ++p) {
+    TransferArgs<T> a{};
+    int64_t inner = 1;
+    for (int q = p + 1; q < D; ++q) inner *= Jc;
+    int64_t outer = 1;
+    for (int q = 0; q < p; ++q) outer *= Jf;
+    a.in = in;
+    a.out = (p == D - 1) ? out : bufs[p % 2];
+    a.Kout = outer * Jf * inner;
+    a.inner = inner;
+    a.Jc = Jc; a.Jf = Jf;
+    a.subtract = (p == D - 1 && subtract) ? 1 : 0;
+    hip_check(launch_transfer<T>(true, a, P->stream), "prolongation pass");
+    in = a.out;
+  }
+}
+template void prolong_op<double>(Problem*, int, const double*, double*, bool);
+template void prolong_op<float>(Problem*, int, const float*, float*, bool);
+
+// out (level g-1) = I' r (level g).
+template <typename T>
+void restrict_op(Problem* P, int g, const T* r, T* out) {
+  const int D = P->d;
+  const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
+  T* X = prob_xfer<T>(P);
+  T* bufs[2] = {X, X + P->lev[P->G].K};
+  const T* in = r;
+  for (int p = 0; p < D; ++p) {
+    TransferArgs<T> a{};
+    int64_t inner = 1;
+    for (int q = p + 1; q < D; ++q) inner *= Jf;
+    int64_t outer = 1;
+    for (int q = 0; q < p; ++q) outer *= Jc;
+    a.in = in;
+    a.out = (p == D - 1) ? out : bufs[p % 2];
+    a.Kout = outer * Jc * inner;
+    a.inner = inner;
+    a.Jc = Jc; a.Jf = Jf;
+    a.subtract = 0;
+    hip_check(launch_transfer<T>(false, a, P->stream), "restriction pass");
+    in = a.out;
+  }
+}
+template void restrict_op<double>(Problem*, int, const double*, double*);
+template void restrict_op<float>(Problem*, int, const float*, float*);
+
+// x = A_1^-1 b with the precomputed inverse B and one refinement step:
+// x1 = B b, r = b - A_1 x1, x = x1 + B r (all FP64), so the result is as
+// accurate as a backward-stable solve would give.
+template <typename T>
+void coarse_op(Problem* P, const T* b, T* x) {
+  const int K = P->K1;
+  double* x1 = P->cwork.p;
+  double* r = P->cwork.p + K;
+  hip_check(launch_gemv<double, T, double>(P->A1inv.p, K, nullptr, 1.0, b, x1, P->stream), "coarse solve");
+  hip_check(launch_gemv<T, double, double>(P->A1.p, K, b, -1.0, x1, r, P->stream), "coarse residual");
+  hip_check(launch_gemv<double, double, T>(P->A1inv.p, K, x1, 1.0, r, x, P->stream), "coarse correction");
+}
+template void coarse_op<double>(Problem*, const double*, double*);
+template void coarse_op<float>(Problem*, const float*, float*);
+
+// One V-cycle (Alg. 7) on level g from a zero start: alpha = B_g b.
+template <typename T>
+void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
+  if (g == 1) {
+    coarse_op<T>(P, b, alpha);
+    return;
+  }
+  Level& L = P->lev[g];
+  const int64_t K = L.K;
+  T* t = lvl_t<T>(L);
+  const T* w = lvl_w<T>(L);
+  const int nu1 = P->opt.nu1, nu2 = P->opt.nu2;
+  // pre-smoothing (Alg. 6); the first sweep from zero needs no apply
+  if (nu1 >= 1) {
+    hip_check(launch_jacobi_first<T>(alpha, w, b, K, P->stream), "jacobi");
+    for (int j = 1; j < nu1; ++j) {
+      apply_op<T>(P, g, alpha, t);
+      hip_check(launch_jacobi<T>(alpha, w, b, t, K, P->stream), "jacobi");
+    }
+  } else {
+    hip_check(launch_fill<T>(alpha, T(0), K, P->stream), "fill");
+  }
+  // r = A alpha - b, restricted
+  apply_op<T>(P, g, alpha, t);
+  hip_check(launch_residual<T>(t, t, b, K, P->stream), "residual");
+  Level& C = P->lev[g - 1];
+  restrict_op<T>(P, g, t, lvl_b<T>(C));
+  vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
+  // alpha -= I e
+  prolong_op<T>(P, g, lvl_a<T>(C), alpha, true);
+  // post-smoothing
+  for (int j = 0; j < nu2; ++j) {
+    apply_op<T>(P, g, alpha, t);
+    hip_check(launch_jacobi<T>(alpha, w, b, t, K, P->stream), "jacobi");
+  }
+}
+template void vcycle_op<double>(Problem*, int, const double*, double*);
+template void vcycle_op<float>(Problem*, int, const float*, float*);
+
+// Times `reps` launches of the Lambda passes and of the point pass of A_g.
+template <typename T>
+void profile_apply(Problem* P, int g, int reps, double* ms_lambda, double* ms_data) {
+  Level& L = P->lev[g];
+  T* c = lvl_a<T>(L);
+  T* out = lvl_t<T>(L);
+  hip_check(launch_fill<T>(c, T(0.5), L.K, P->stream), "fill");
+  hipEvent_t e0, e1, e2;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  hip_check(hipEventCreate(&e2), "event");
+  const bool fp32 = sizeof(T) == 4;
+  const DataArgs a = data_args(P, g, fp32, c, out);
+  hip_check(hipEventRecord(e0, P->stream), "record");
+  for (int i = 0; i < reps; ++i) lambda_apply<T>(P, g, c, out);
+  hip_check(hipEventRecord(e1, P->stream), "record");
+  for (int i = 0; i < reps; ++i) hip_check(launch_data(P->d, fp32, kApply, a, P->stream), "data pass");
+  hip_check(hipEventRecord(e2, P->stream), "record");
+  hip_check(hipEventSynchronize(e2), "sync");
+  float t01 = 0.f, t12 = 0.f;
+  hip_check(hipEventElapsedTime(&t01, e0, e1), "elapsed");
+  hip_check(hipEventElapsedTime(&t12, e1, e2), "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  *ms_lambda = double(t01) / reps;
+  *ms_data = double(t12) / reps;
+}
+template void profile_apply<double>(Problem*, int, int, double*, double*);
+template void profile_apply<float>(Problem*, int, int, double*, double*);
+
+// ---------------------------------------------------------------------------
+// Device scalars: dots go to slots; read back with one synchronising copy.
+double* Problem::slot(int i) { return slots.p + i; }
+
+void Problem::read_slots(int first, int count, double* host) {
+  hip_check(hipMemcpyAsync(host_slots + first, slots.p + first, sizeof(double) * count, hipMemcpyDeviceToHost,
+                           stream),
+            "slot readback");
+  hip_check(hipStreamSynchronize(stream), "stream sync");
+  std::memcpy(host, host_slots + first, sizeof(double) * count);
+}
+
+template <typename TX, typename TY>
+void dot_op(Problem* P, const TX* x, const TY* y, int64_t K, int slot) {
+  hip_check(launch_dot<TX, TY>(x, y, K, P->partial.p, P->slot(slot), P->stream), "dot");
+}
+template void dot_op<double, double>(Problem*, const double*, const double*, int64_t, int);
+template void dot_op<float, float>(Problem*, const float*, const float*, int64_t, int);
+
+// ---------------------------------------------------------------------------
+// Setup.
+static int tile_bits_for(int D) {
+  switch (D) {
+    case 1: return 6;
+    case 2: return 4;
+    case 3: return 2;
+    default: return 1;
+  }
+}
+
+static void compute_diag(Problem* P, int g) {
+  Level& L = P->lev[g];
+  hip_check(launch_lambda_diag(P->d, L.band64.p, L.J, L.K, P->lam, L.diag.p, P->stream), "lambda diag");
+  hip_check(launch_data(P->d, false, kDiag, data_args(P, g, false, nullptr, L.diag.p), P->stream), "data diag");
+}
+
+// theta_g: largest Ritz value of `steps` Lanczos steps on D^-1/2 A_g D^-1/2
+// from the fixed start u[k] = frac(k * 2654435761 / 2^32) - 1/2.
+static double lanczos_theta(Problem* P, int g, int steps) {
+  Level& L = P->lev[g];
+  const int64_t K = L.K;
+  double* dis = P->vb.p;   // PCG vectors double as work space during setup
+  double* v = P->vr.p;
+  double* vprev = P->vz.p;
+  double* w = P->vp.p;
+  double* y = P->vv.p;
+  double* Ay = L.t64.p;
+  hip_check(launch_rsqrt_vec(L.diag.p, dis, K, P->stream), "rsqrt");
+  hip_check(launch_start_vector(w, K, P->stream), "start");
+  dot_op<double, double>(P, w, w, K, 0);
+  double nrm2;
+  P->read_slots(0, 1, &nrm2);
+  hip_check(launch_scale_copy<double, double>(w, v, K, 1.0 / std::sqrt(nrm2), nullptr, P->stream), "scale");
+  hip_check(launch_fill<double>(vprev, 0.0, K, P->stream), "fill");
+  std::vector<double> al, be;
+  double beta_prev = 0.0;
+  const int m = int(std::min<int64_t>(steps, K));
+  for (int j = 0; j < m; ++j) {
+    hip_check(launch_mul(dis, v, y, K, P->stream), "mul");
+    apply_op<double>(P, g, y, Ay);
+    hip_check(launch_lanczos_w(dis, Ay, vprev, beta_prev, w, K, P->stream), "lanczos");
+    dot_op<double, double>(P, w, v, K, 0);
+    double a;
+    P->read_slots(0, 1, &a);
+    hip_check(launch_axpy(-a, v, w, K, P->stream), "axpy");
+    dot_op<double, double>(P, w, w, K, 0);
+    double b2;
+    P->read_slots(0, 1, &b2);
+    al.push_back(a);
+    const double b = std::sqrt(b2);
+    if (j == m - 1 || b <= 1e-12 * std::fabs(a)) break;
+    be.push_back(b);
+    std::swap(vprev, v);   // vprev <- v
+    hip_check(launch_scale_copy<double, double>(w, v, K, 1.0 / b, nullptr, P->stream), "scale");
+    beta_prev = b;
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  return tridiag_max_eig(al, be);
+}
+
+// A_1 = sum over level-1 cells of the cell Gram (from moments) + lambda
+// Lambda_1, then its inverse by Gauss-Jordan; pivots checked for positivity.
+static void build_coarse(Problem* P) {
+  const int D = P->d;
+  const int cells = 1 << D;
+  int64_t e7 = 1;
+  for (int p = 0; p < D; ++p) e7 *= 7;
+  const int64_t K1 = P->lev[1].K;
+  P->K1 = int(K1);
+  DevBuf<double> mom, bufA, bufB, ctab, row, col, piv;
+  mom.alloc(size_t(cells) * e7);
+  hip_check(launch_fill<double>(mom.p, 0.0, int64_t(cells) * e7, P->stream), "fill");
+  int chunks = int(std::min<int64_t>(64, std::max<int64_t>(1, P->n / (int64_t(cells) * 32768))));
+  hip_check(launch_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, chunks, mom.p, P->stream), "moments");
+  std::vector<double> ct;
+  pair_table(ct);
+  ctab.alloc(ct.size());
+  hip_check(hipMemcpyAsync(ctab.p, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, P->stream),
+            "upload");
+  // contraction buffers: step p output = cells * 16^(p+1) * 7^(D-1-p)
+  int64_t maxsz = 0;
+  {
+    int64_t a16 = 1, r7 = e7;
+    for (int p = 0; p < D; ++p) {
+      r7 /= 7;
+      a16 *= 16;
+      maxsz = std::max(maxsz, int64_t(cells) * a16 * r7);
+    }
+  }
+  bufA.alloc(size_t(maxsz));
+  bufB.alloc(size_t(maxsz));
+  const double* in = mom.p;
+  int64_t a16 = 1, r7 = e7;
+  double* outp = nullptr;
+  for (int p = 0; p < D; ++p) {
+    r7 /= 7;
+    outp = (p % 2 == 0) ? bufA.p : bufB.p;
+    hip_check(launch_contract(in, outp, ctab.p, int64_t(cells) * a16, r7, P->stream), "contract");
+    a16 *= 16;
+    in = outp;
+  }
+  P->A1.alloc(size_t(K1) * K1);
+  P->A1inv.alloc(size_t(K1) * K1);
+  P->cwork.alloc(size_t(2 * K1));
+  hip_check(launch_assemble_a1(D, outp, P->lev[1].band64.p, P->lam, P->A1.p, int(K1), P->stream), "assemble");
+  hip_check(hipMemcpyAsync(P->A1inv.p, P->A1.p, sizeof(double) * K1 * K1, hipMemcpyDeviceToDevice, P->stream),
+            "copy A1");
+  // diagonal before inversion, for the pivot test
+  std::vector<double> a1(size_t(K1) * K1);
+  hip_check(hipMemcpyAsync(a1.data(), P->A1inv.p, a1.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream),
+            "download");
+  hip_check(hipStreamSynchronize(P->stream), "sync");
+  row.alloc(size_t(K1));
+  col.alloc(size_t(K1));
+  piv.alloc(size_t(K1));
+  for (int k = 0; k < K1; ++k)
+    hip_check(launch_gj_step(P->A1inv.p, int(K1), k, row.p, col.p, piv.p, P->stream), "gauss-jordan");
+  hip_check(launch_symmetrize(P->A1inv.p, int(K1), P->stream), "symmetrize");
+  std::vector<double> pv(static_cast<size_t>(K1));
+  hip_check(hipMemcpyAsync(pv.data(), piv.p, pv.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream),
+            "download");
+  hip_check(hipStreamSynchronize(P->stream), "sync");
+  for (int64_t k = 0; k < K1; ++k) {
+    const double dkk = a1[size_t(k) * K1 + k];
+    if (!std::isfinite(pv[k]) || !(pv[k] > 1e-13 * dkk)) {
+      throw Error{TS_ESINGULAR,
+                  "coarse matrix A_1 is not positive definite (pivot " + std::to_string(k) + " = " +
+                      std::to_string(pv[k]) + "): some affine function vanishes at every data point"};
+    }
+  }
+}
+
+Problem* create_problem(int d, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
+                        const double* x, const double* y, double lam, const ts_options* opt) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (d < 1 || d > kMaxDim) throw Error{TS_EINVAL, "d must be in 1..5"};
+  if (!intervals || !lo || !hi || !x || !y) throw Error{TS_EINVAL, "null argument"};
+  if (n < 1) throw Error{TS_EINVAL, "n must be >= 1"};
+  if (!(lam > 0.0) || !std::isfinite(lam)) throw Error{TS_EINVAL, "lambda must be finite and > 0"};
+  const int N = intervals[0];
+  for (int p = 0; p < d; ++p) {
+    if (intervals[p] != N) throw Error{TS_EINVAL, "all dimensions must have the same number of intervals"};
+    if (!(lo[p] < hi[p]) || !std::isfinite(lo[p]) || !std::isfinite(hi[p]))
+      throw Error{TS_EINVAL, "box must satisfy lo < hi with finite bounds"};
+  }
+  if (N < 2 || (N & (N - 1)) != 0) throw Error{TS_EINVAL, "intervals must be a power of two >= 2"};
+  int G = 0;
+  while ((1 << G) < N) ++G;
+  if (int64_t(G) * d > 30) throw Error{TS_EINVAL, "N^d must not exceed 2^30 cells"};
+  {
+    double K = std::pow(double(N + kDeg), d);
+    if (K >= 2147483647.0) throw Error{TS_EINVAL, "(N+3)^d must be < 2^31"};
+  }
+  if (n > 2000000000LL) throw Error{TS_EINVAL, "n must be < 2e9"};
+
+  Problem* P = new Problem();
+  try {
+    P->d = d;
+    P->G = G;
+    P->N = N;
+    P->n = n;
+    P->lam = lam;
+    ts_default_options(&P->opt);
+    if (opt) P->opt = *opt;
+    if (P->opt.nu1 < 0 || P->opt.nu2 < 0) throw Error{TS_EINVAL, "nu1, nu2 must be >= 0"};
+    if (P->opt.precision != TS_FP64 && P->opt.precision != TS_MIXED_FP32)
+      throw Error{TS_EINVAL, "unknown or unavailable precision"};
+    if (!(P->opt.tol > 0.0)) throw Error{TS_EINVAL, "tol must be > 0"};
+    if (P->opt.omega_fixed <= 0.0 && !(P->opt.omega_scale > 0.0 && P->opt.omega_scale < 2.0))
+      throw Error{TS_EINVAL, "omega_scale must be in (0, 2)"};
+    hip_check(hipGetDevice(&P->device), "hipGetDevice");
+    if (P->opt.stream) {
+      P->stream = static_cast<hipStream_t>(P->opt.stream);
+    } else {
+      hip_check(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking), "stream");
+      P->own_stream = true;
+    }
+    hip_check(hipHostMalloc(reinterpret_cast<void**>(&P->host_slots), sizeof(double) * kSlots), "pinned");
+    P->slots.alloc(kSlots);
+    P->partial.alloc(kMaxPartials);
+    P->flag.alloc(1);
+    for (int p = 0; p < d; ++p) {
+      P->box.lo[p] = lo[p];
+      P->box.hi[p] = hi[p];
+      P->box.inv_h[p] = double(N) / (hi[p] - lo[p]);
+    }
+    P->box.G = G;
+    hipStream_t st = P->stream;
+
+    // --- bin, validate, sort, place (points in Morton order of their cell)
+    {
+      DevBuf<uint32_t> key0, key1, idx0, idx1;
+      key0.alloc(size_t(n));
+      key1.alloc(size_t(n));
+      idx0.alloc(size_t(n));
+      idx1.alloc(size_t(n));
+      hip_check(launch_fill<int>(P->flag.p, 0, 1, st), "fill");
+      hip_check(launch_bin(d, x, n, P->box, key0.p, idx0.p, P->flag.p, st), "bin");
+      hip_check(launch_check_finite(y, n, P->flag.p, st), "check y");
+      int flag = 0;
+      hip_check(hipMemcpyAsync(&flag, P->flag.p, sizeof(int), hipMemcpyDeviceToHost, st), "flag");
+      hip_check(hipStreamSynchronize(st), "sync");
+      if (flag & 2) throw Error{TS_EINVAL, "x contains non-finite values"};
+      if (flag & 4) throw Error{TS_EINVAL, "some points lie outside [lo, hi]"};
+      if (flag & 1) throw Error{TS_EINVAL, "y contains non-finite values"};
+      size_t tmp_bytes = 0;
+      hip_check(sort_pairs(key0.p, key1.p, idx0.p, idx1.p, n, G * d, nullptr, &tmp_bytes, st), "sort size");
+      DevBuf<unsigned char> tmp;
+      tmp.alloc(tmp_bytes + 16);
+      hip_check(sort_pairs(key0.p, key1.p, idx0.p, idx1.p, n, G * d, tmp.p, &tmp_bytes, st), "sort");
+      P->t64.alloc(size_t(n) * d);
+      P->t32.alloc(size_t(n) * d);
+      P->cell.alloc(size_t(n));
+      P->ys.alloc(size_t(n));
+      hip_check(launch_place(d, x, y, idx1.p, n, P->box, P->t64.p, P->t32.p, P->cell.p, P->ys.p, st), "place");
+      const int64_t ncells = int64_t(1) << (G * d);
+      P->off.alloc(size_t(ncells + 1));
+      hip_check(launch_offsets(key1.p, n, ncells, P->off.p, st), "offsets");
+      hip_check(hipStreamSynchronize(st), "sync");
+      P->mkey = std::move(key1);
+    }
+
+    // --- data-term work split
+    // (the point pass sizes its item lists for at most 2048 points per workgroup)
+    if (P->opt.points_per_block > 0) {
+      P->ppb = std::max(64, std::min(2048, P->opt.points_per_block));
+    } else {
+      int64_t ppb = (n + 4095) / 4096;
+      ppb = ((ppb + 63) / 64) * 64;
+      P->ppb = int(std::max<int64_t>(256, std::min<int64_t>(2048, ppb)));
+    }
+
+    // --- levels g = 1..G (N_g = 2^g)
+    P->lev.resize(G + 1);
+    const int64_t KG = [&] { int64_t K = 1; for (int p = 0; p < d; ++p) K *= (N + kDeg); return K; }();
+    for (int g = 1; g <= G; ++g) {
+      Level& L = P->lev[g];
+      L.g = g;
+      L.N = 1 << g;
+      L.J = L.N + kDeg;
+      L.K = 1;
+      for (int p = 0; p < d; ++p) L.K *= L.J;
+      L.tb = std::min(tile_bits_for(d), g);
+      std::vector<double> band(size_t(d) * 3 * L.J * 7);
+      for (int p = 0; p < d; ++p) {
+        std::vector<double> b1;
+        gram_band(lo[p], hi[p], L.N, b1);
+        std::copy(b1.begin(), b1.end(), band.begin() + size_t(p) * 3 * L.J * 7);
+      }
+      std::vector<float> bandf(band.begin(), band.end());
+      L.band64.alloc(band.size());
+      L.band32.alloc(band.size());
+      hip_check(hipMemcpyAsync(L.band64.p, band.data(), band.size() * 8, hipMemcpyHostToDevice, st), "upload");
+      hip_check(hipMemcpyAsync(L.band32.p, bandf.data(), bandf.size() * 4, hipMemcpyHostToDevice, st), "upload");
+      L.diag.alloc(size_t(L.K));
+      L.wdinv64.alloc(size_t(L.K));
+      L.wdinv32.alloc(size_t(L.K));
+      L.a64.alloc(size_t(L.K));
+      L.b64.alloc(size_t(L.K));
+      L.t64.alloc(size_t(L.K));
+      L.a32.alloc(size_t(L.K));
+      L.b32.alloc(size_t(L.K));
+      L.t32.alloc(size_t(L.K));
+      hip_check(hipStreamSynchronize(st), "sync");   // host band vectors go out of scope
+    }
+    P->lamS64.alloc(size_t(6 * KG));
+    P->lamS32.alloc(size_t(6 * KG));
+    P->xfer64.alloc(size_t(2 * KG));
+    P->xfer32.alloc(size_t(2 * KG));
+    P->vb.alloc(size_t(KG));
+    P->vr.alloc(size_t(KG));
+    P->vz.alloc(size_t(KG));
+    P->vp.alloc(size_t(KG));
+    P->vv.alloc(size_t(KG));
+    P->r32.alloc(size_t(KG));
+    P->z32.alloc(size_t(KG));
+    P->p32.alloc(size_t(KG));
+    P->v32.alloc(size_t(KG));
+    P->d32.alloc(size_t(KG));
+
+    // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)
+    for (int g = 1; g <= G; ++g) compute_diag(P, g);
+    for (int g = 2; g <= G; ++g) {
+      Level& L = P->lev[g];
+      if (P->opt.omega_fixed > 0.0) {
+        L.omega = P->opt.omega_fixed;
+      } else {
+        L.theta = lanczos_theta(P, g, std::max(1, P->opt.lanczos_steps));
+        L.omega = P->opt.omega_scale / L.theta;
+      }
+      hip_check(launch_wdinv(L.diag.p, L.omega, L.wdinv64.p, L.wdinv32.p, L.K, st), "wdinv");
+    }
+
+    // --- coarse level (Sec. 3.2.4)
+    build_coarse(P);
+    hip_check(hipStreamSynchronize(st), "sync");
+    P->applies = 0;
+    P->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return P;
+  } catch (...) {
+    delete P;
+    throw;
+  }
+}
+
+Problem::~Problem() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  lev.clear();
+  if (host_slots) (void)hipHostFree(host_slots);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace tsmg

@@ -1,0 +1,133 @@
+// Internal state of one smoothing problem (host-side view of device memory).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/tsmg.h"
+#include "launch.h"
+
+namespace tsmg {
+
+struct Error {
+  ts_status code;
+  std::string msg;
+};
+
+void hip_check(hipError_t e, const char* what);
+void set_error(const std::string& m);
+
+// Owning device buffer (freed on destruction). Allocation failure throws
+// Error{TS_ENOMEM}.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevBuf() { reset(); }
+  void alloc(size_t count) {
+    reset();
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{TS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct Level {
+  int g = 0, N = 0, J = 0;
+  int64_t K = 0;
+  int tb = 0;                      // tile side 2^tb cells per dimension in the point pass
+  double theta = 0.0, omega = 0.0; // Lanczos estimate and Jacobi damping
+  DevBuf<double> band64;           // [d][3][J][7] banded M, G1, G2 per dimension
+  DevBuf<float> band32;
+  DevBuf<double> diag;             // diag(A_g)
+  DevBuf<double> wdinv64;          // omega_g / diag(A_g)
+  DevBuf<float> wdinv32;
+  DevBuf<double> a64, b64, t64;    // V-cycle iterate, right-hand side, A x work vector
+  DevBuf<float> a32, b32, t32;
+};
+
+constexpr int kSlots = 16;
+
+struct Problem {
+  int device = 0;
+  int d = 0, G = 0, N = 0;
+  int64_t n = 0;
+  double lam = 0.0;
+  ts_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  BoxArgs box{};
+  int ppb = 256;
+
+  // points in Morton order of their finest cell
+  DevBuf<double> t64;       // [d][n] position inside the finest cell
+  DevBuf<float> t32;        // [d][n]
+  DevBuf<uint32_t> cell;    // [n] finest cell, C order
+  DevBuf<uint32_t> mkey;    // [n] finest cell, Morton order (sorted)
+  DevBuf<double> ys;        // [n] responses
+  DevBuf<int32_t> off;      // [N^d + 1] Morton cell offsets
+
+  std::vector<Level> lev;   // index 1..G
+  DevBuf<double> lamS64;    // 6 K_G: two sets of (T0, T1, T2)
+  DevBuf<float> lamS32;
+  DevBuf<double> xfer64;    // 2 K_G: transfer intermediates
+  DevBuf<float> xfer32;
+  DevBuf<double> A1;        // K_1 x K_1 coarse matrix (for the refinement step)
+  DevBuf<double> A1inv;     // K_1 x K_1 inverse of the coarse matrix
+  DevBuf<double> cwork;     // 2 K_1 coarse-solve work space
+  int K1 = 0;
+
+  // solver vectors on the finest level
+  DevBuf<double> vb, vr, vz, vp, vv;
+  DevBuf<float> r32, z32, p32, v32, d32;
+
+  DevBuf<double> slots;     // device scalars
+  DevBuf<double> partial;   // reduction partials
+  DevBuf<int> flag;
+  double* host_slots = nullptr;
+
+  double setup_s = 0.0;
+  int64_t applies = 0;
+
+  double* slot(int i);
+  void read_slots(int first, int count, double* host);
+  ~Problem();
+};
+
+Problem* create_problem(int d, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
+                        const double* x, const double* y, double lam, const ts_options* opt);
+
+template <typename T> void apply_op(Problem* P, int g, const T* c, T* out);
+template <typename T> void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract);
+template <typename T> void restrict_op(Problem* P, int g, const T* r, T* out);
+template <typename T> void coarse_op(Problem* P, const T* b, T* x);
+template <typename T> void vcycle_op(Problem* P, int g, const T* b, T* alpha);
+template <typename T> void profile_apply(Problem* P, int g, int reps, double* ms_lambda, double* ms_data);
+template <typename TX, typename TY> void dot_op(Problem* P, const TX* x, const TY* y, int64_t K, int slot);
+
+ts_status solve(Problem* P, double* alpha, int use_start, ts_solve_info* info);
+
+}  // namespace tsmg
+
+struct ts_problem {
+  tsmg::Problem* impl;
+};

@@ -1,0 +1,202 @@
+// Krylov drivers: MGCG (Alg. 8) in FP64 and the mixed-precision refinement
+// loop around an FP32 MGCG. Scalars stay on the device; each iteration reads
+// back p'v and r'r once for the breakdown and stopping tests.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <utility>
+
+#include "problem.h"
+
+namespace tsmg {
+
+namespace {
+
+enum Slot : int { kScratch = 0, kBB = 1, kRZa = 2, kRZb = 3, kPV = 4, kRR = 5, kRR64 = 6 };
+
+void rhs_into(Problem* P, double* b) {
+  const int64_t K = P->lev[P->G].K;
+  hip_check(launch_fill<double>(b, 0.0, K, P->stream), "fill");
+  DataArgs a{};
+  a.tfrac = P->t64.p;
+  a.cell = P->cell.p;
+  a.mkey = P->mkey.p;
+  a.y = P->ys.p;
+  a.off = P->off.p;
+  a.c = nullptr;
+  a.out = b;
+  a.n = P->n;
+  a.G = P->G;
+  a.g = P->G;
+  a.tb = P->lev[P->G].tb;
+  a.ppb = P->ppb;
+  hip_check(launch_data(P->d, false, kRhs, a, P->stream), "rhs");
+}
+
+// r = b - A alpha (FP64); uses v as work space.
+void true_residual(Problem* P, const double* alpha, const double* b, double* r, double* v) {
+  const int64_t K = P->lev[P->G].K;
+  apply_op<double>(P, P->G, alpha, v);
+  hip_check(launch_residual<double>(r, v, b, K, P->stream), "residual");       // r = Av - b
+  hip_check(launch_scale_copy<double, double>(r, r, K, -1.0, nullptr, P->stream), "negate");
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+void rhs_op(Problem* P, double* b) { rhs_into(P, b); }
+
+static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_info* info) {
+  const int G = P->G;
+  const int64_t K = P->lev[G].K;
+  hipStream_t st = P->stream;
+  double *b = P->vb.p, *r = P->vr.p, *z = P->vz.p, *p = P->vp.p, *v = P->vv.p;
+  rhs_into(P, b);
+  dot_op<double, double>(P, b, b, K, kBB);
+  double bb;
+  P->read_slots(kBB, 1, &bb);
+  if (!std::isfinite(bb)) throw Error{TS_EBREAKDOWN, "right-hand side is not finite"};
+  if (bb == 0.0) {
+    hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
+    info->converged = 1;
+    info->rel_residual = 0.0;
+    return TS_OK;
+  }
+  const double bnorm = std::sqrt(bb);
+  if (use_start) {
+    true_residual(P, alpha, b, r, v);
+  } else {
+    hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
+    hip_check(launch_scale_copy<double, double>(b, r, K, 1.0, nullptr, st), "copy");
+  }
+  const double tol = P->opt.tol;
+  int total = 0, restarts = 0;
+  double rel_true = 1.0;
+  for (;;) {
+    int sa = kRZa, sb = kRZb;
+    vcycle_op<double>(P, G, r, z);
+    hip_check(launch_scale_copy<double, double>(z, p, K, 1.0, nullptr, st), "copy");
+    dot_op<double, double>(P, r, z, K, sa);
+    while (total < P->opt.max_iter) {
+      apply_op<double>(P, G, p, v);
+      dot_op<double, double>(P, p, v, K, kPV);
+      hip_check(launch_cg_step<double, double>(alpha, r, p, v, K, P->slot(sa), P->slot(kPV), st), "cg step");
+      dot_op<double, double>(P, r, r, K, kRR);
+      double h[2];
+      P->read_slots(kPV, 2, h);
+      ++total;
+      if (!finite_pos(h[0]) || !std::isfinite(h[1]))
+        throw Error{TS_EBREAKDOWN, "CG breakdown: p'Ap = " + std::to_string(h[0])};
+      if (std::sqrt(h[1]) / bnorm <= tol) break;
+      vcycle_op<double>(P, G, r, z);
+      dot_op<double, double>(P, r, z, K, sb);
+      hip_check(launch_p_update<double>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
+      std::swap(sa, sb);
+    }
+    // confirm with the true FP64 residual; restart from it if the recursive
+    // residual drifted below the tolerance first
+    true_residual(P, alpha, b, r, v);
+    dot_op<double, double>(P, r, r, K, kRR);
+    double rr;
+    P->read_slots(kRR, 1, &rr);
+    rel_true = std::sqrt(rr) / bnorm;
+    if (rel_true <= tol || total >= P->opt.max_iter || restarts >= 5) break;
+    ++restarts;
+  }
+  info->iterations = total;
+  info->refinements = restarts;
+  info->rel_residual = rel_true;
+  info->converged = rel_true <= tol;
+  return info->converged ? TS_OK : TS_ENOTCONV;
+}
+
+// Iterative refinement: FP64 residual, FP32 MGCG correction on the
+// normalised residual, FP64 update.
+static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_info* info) {
+  const int G = P->G;
+  const int64_t K = P->lev[G].K;
+  hipStream_t st = P->stream;
+  double *b = P->vb.p, *r = P->vr.p, *v = P->vv.p;
+  float *rin = P->r32.p, *z = P->z32.p, *p = P->p32.p, *w = P->v32.p, *dl = P->d32.p;
+  rhs_into(P, b);
+  dot_op<double, double>(P, b, b, K, kBB);
+  double bb;
+  P->read_slots(kBB, 1, &bb);
+  if (!std::isfinite(bb)) throw Error{TS_EBREAKDOWN, "right-hand side is not finite"};
+  if (bb == 0.0) {
+    hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
+    info->converged = 1;
+    info->rel_residual = 0.0;
+    return TS_OK;
+  }
+  const double bnorm = std::sqrt(bb);
+  if (!use_start) hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
+  const double tol = P->opt.tol;
+  int inner_total = 0, refine = 0;
+  double rel = 1.0;
+  bool first = true;
+  for (;;) {
+    if (first && !use_start) {
+      hip_check(launch_scale_copy<double, double>(b, r, K, 1.0, nullptr, st), "copy");
+    } else {
+      true_residual(P, alpha, b, r, v);
+    }
+    first = false;
+    dot_op<double, double>(P, r, r, K, kRR64);
+    double rr;
+    P->read_slots(kRR64, 1, &rr);
+    if (!std::isfinite(rr)) throw Error{TS_EBREAKDOWN, "residual is not finite"};
+    rel = std::sqrt(rr) / bnorm;
+    if (rel <= tol || inner_total >= P->opt.max_iter || refine >= P->opt.max_refine) break;
+    // inner FP32 MGCG on r / ||r||
+    hip_check(launch_scale_copy<double, float>(r, rin, K, 1.0, P->slot(kRR64), st), "to fp32");
+    hip_check(launch_fill<float>(dl, 0.0f, K, st), "fill");
+    int sa = kRZa, sb = kRZb;
+    vcycle_op<float>(P, G, rin, z);
+    hip_check(launch_scale_copy<float, float>(z, p, K, 1.0, nullptr, st), "copy");
+    dot_op<float, float>(P, rin, z, K, sa);
+    for (;;) {
+      apply_op<float>(P, G, p, w);
+      dot_op<float, float>(P, p, w, K, kPV);
+      hip_check(launch_cg_step<float, float>(dl, rin, p, w, K, P->slot(sa), P->slot(kPV), st), "cg step");
+      dot_op<float, float>(P, rin, rin, K, kRR);
+      double h[2];
+      P->read_slots(kPV, 2, h);
+      ++inner_total;
+      if (!finite_pos(h[0]) || !std::isfinite(h[1]))
+        throw Error{TS_EBREAKDOWN, "inner CG breakdown: p'Ap = " + std::to_string(h[0])};
+      if (std::sqrt(h[1]) <= P->opt.inner_tol || inner_total >= P->opt.max_iter) break;
+      vcycle_op<float>(P, G, rin, z);
+      dot_op<float, float>(P, rin, z, K, sb);
+      hip_check(launch_p_update<float>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
+      std::swap(sa, sb);
+    }
+    // alpha += ||r|| * delta
+    hip_check(launch_axpy_conv<float, double>(dl, alpha, K, 1.0, P->slot(kRR64), st), "update");
+    ++refine;
+  }
+  info->iterations = inner_total;
+  info->refinements = refine;
+  info->rel_residual = rel;
+  info->converged = rel <= tol;
+  return info->converged ? TS_OK : TS_ENOTCONV;
+}
+
+ts_status solve(Problem* P, double* alpha, int use_start, ts_solve_info* info_out) {
+  auto t0 = std::chrono::steady_clock::now();
+  ts_solve_info info{};
+  const int64_t applies0 = P->applies;
+  ts_status s;
+  if (P->opt.precision == TS_FP64) s = solve_fp64(P, alpha, use_start, &info);
+  else s = solve_mixed(P, alpha, use_start, &info);
+  hip_check(hipStreamSynchronize(P->stream), "sync");
+  info.setup_s = P->setup_s;
+  info.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  info.applies = P->applies - applies0;
+  if (info_out) *info_out = info;
+  return s;
+}
+
+}  // namespace tsmg

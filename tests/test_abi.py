@@ -1,0 +1,70 @@
+"""The C ABI library loads and exports every entry point include/tsmg.h
+declares; host-side argument checks run without a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1901_00654_amd import tsmg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsmg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ts_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def built():
+    if not os.path.exists(tsmg.LIB_PATH):
+        from paper_1901_00654_amd import build
+        build.build()
+    return tsmg.load_library()
+
+
+def test_exports_every_declared_symbol(built):
+    lib = ctypes.CDLL(tsmg.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(tsmg.exported_symbols())
+
+
+def test_defaults_and_version(built):
+    o = tsmg.ts_default_options()
+    assert (o.nu1, o.nu2, o.lanczos_steps, o.precision) == (2, 2, 16, tsmg.TS_FP64)
+    assert o.omega_scale == 1.5 and o.tol == 1e-8 and o.stream is None
+    assert "gfx950" in tsmg.ts_version()
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(q=2), "cubic"),
+    (dict(lam=0.0), "lambda"),
+    (dict(lam=float("nan")), "lambda"),
+    (dict(intervals=[6, 6]), "power of two"),
+    (dict(intervals=[8, 16]), "same number"),
+    (dict(d=6, intervals=[8] * 6, lo=[0] * 6, hi=[1] * 6), "d must"),
+    (dict(n=0), "n must"),
+    (dict(hi=[1.0, -1.0]), "box"),
+])
+def test_create_rejects_bad_arguments_before_touching_the_device(built, kw, msg):
+    args = dict(d=2, q=3, intervals=[8, 8], lo=[0.0, 0.0], hi=[1.0, 1.0], n=10, x=8, y=8, lam=1e-3)
+    args.update(kw)
+    with pytest.raises(tsmg.TsmgError) as e:
+        tsmg.ts_create(args["d"], args["q"], args["intervals"], args["lo"], args["hi"], args["n"],
+                       args["x"], args["y"], args["lam"])
+    assert e.value.status == tsmg.TS_EINVAL
+    assert msg in str(e.value)
+    assert msg in tsmg.ts_last_error()
+
+
+def test_null_handle_is_rejected(built):
+    with pytest.raises(tsmg.TsmgError) as e:
+        tsmg.ts_num_levels(None)
+    assert e.value.status == tsmg.TS_EINVAL
+    tsmg.ts_destroy(None)

@@ -1,0 +1,47 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark uses: sampled entries of A_G c that the oracle computes one by one,
+and the FP64 true residual of the solves recomputed by the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import gpu_cases as gc
+from oracle import matfree
+from paper_1901_00654_amd import tsmg, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=["c1", "c2", "c3", "c4"])
+def full(request, lib):
+    w = workloads.CONFIGS[request.param]()
+    print("full-size", request.param, "d", w["d"], "N", w["N"], "n", len(w["y"]), flush=True)
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"])
+    yield w, S
+    S.close()
+
+
+def test_apply_sampled_entries(full):
+    w, S = full
+    rng = np.random.default_rng(300)
+    K = S.K()
+    c = rng.standard_normal(K)
+    out = S.apply(S.G, c).cpu().numpy()
+    ks = np.concatenate([[0, K - 1, K // 2], rng.integers(0, K, 5)])
+    ref = matfree.apply_rows(w["x"], c, w["lo"], w["hi"], w["N"], w["lam"], ks)
+    assert gc.rel(out[ks], ref) < 1e-12
+
+
+@pytest.mark.parametrize("precision", [tsmg.TS_FP64, tsmg.TS_MIXED_FP32])
+def test_solve_true_residual(full, precision):
+    w, S = full
+    if w["name"] in ("c3", "c4"):
+        pytest.skip("full-size C3/C4 solves run in the benchmark; the CPU residual check is too slow here")
+    S.set_options(tol=1e-8, precision=precision, max_iter=20000)
+    alpha, status, info = S.solve()
+    print(w["name"], "precision", precision, info, flush=True)
+    assert status == tsmg.TS_OK and info["rel_residual"] <= 1e-8
+    a = alpha.cpu().numpy()
+    b = matfree.rhs(w["x"], w["y"], w["lo"], w["hi"], w["N"])
+    r = b - matfree.apply(w["x"], a, w["lo"], w["hi"], w["N"], w["lam"])
+    assert np.linalg.norm(r) / np.linalg.norm(b) < 1.5e-8

@@ -170,6 +170,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--only-apply", default=None, metavar="WORKLOAD",
+                    help="only time the finest-level operator apply of one workload (c1..c4), "
+                         "for profiling runs; prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -183,6 +186,18 @@ def main():
     tsmg.load_library()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.only_apply:
+        wk = workloads.CONFIGS[args.only_apply]()
+        res = apply_rate(tsmg, torch, wk, stream, args.reps)
+        if args.copy_calibration:
+            src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            res["copy_calibration_bytes"] = src.numel() * 8
+        print(json.dumps(res), flush=True)
+        return
     w = workloads.c2()
     xd = torch.from_numpy(w["x"]).cuda()
     yd = torch.from_numpy(w["y"]).cuda()

@@ -84,6 +84,11 @@ typedef struct {
     double inner_tol;      /* mixed: relative reduction per refinement step; 1e-4     */
     int max_refine;        /* mixed: refinement steps; default 50                    */
     int points_per_block;  /* data-term work per workgroup; 0 = automatic            */
+    int stencil_mode;      /* levels whose A_g is assembled at setup as a 7^d-point
+                              stencil (same operator, applied as a stencil product):
+                              0 = where it is estimated faster and fits (default),
+                              1 = none (matrix-free on every level),
+                              2 = every level whose stencil fits in memory          */
     void* stream;          /* hipStream_t to enqueue on; NULL = a library stream      */
 } ts_options;
 

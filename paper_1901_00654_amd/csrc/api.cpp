@@ -69,6 +69,7 @@ void ts_default_options(ts_options* o) {
   o->inner_tol = 1e-4;
   o->max_refine = 50;
   o->points_per_block = 0;
+  o->stencil_mode = 0;
   o->stream = nullptr;
 }
 

@@ -8,6 +8,9 @@ namespace tsmg {
 constexpr int kMaxDim = 5;
 constexpr int kDeg = 3;          // cubic B-splines
 constexpr int kBlock = 256;      // threads per workgroup for every kernel
+// Most sorted points one workgroup of the point pass takes, by dimension
+// (bounded by the LDS that stages them).
+constexpr int kMaxPointsPerBlock[kMaxDim + 1] = {0, 2048, 2048, 1024, 1024, 512};
 
 // What the point pass of the data term computes (Alg. 3/4/5):
 enum DataMode : int {
@@ -29,7 +32,7 @@ struct DataArgs {
   int G;                    // finest level (N_G = 2^G)
   int g;                    // this level
   int tb;                   // tile side 2^tb level-g cells per dimension (tb <= g)
-  int ppb;                  // points per workgroup (<= 2048)
+  int ppb;                  // points per workgroup (<= kMaxPointsPerBlock[d])
 };
 
 }  // namespace tsmg

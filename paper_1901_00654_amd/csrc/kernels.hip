@@ -53,6 +53,18 @@ __device__ __forceinline__ void morton_decode(uint32_t key, int bits, int (&c)[D
   }
 }
 
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// blockIdx. This renumbering gives each XCD a contiguous run of logical
+// blocks, so neighbouring point ranges - which share tiles, coefficient
+// patches and output entries - run behind the same L2. It is a bijection of
+// 0..gridDim.x-1.
+__device__ __forceinline__ int xcd_block() {
+  constexpr int kXcd = 8;
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int x = b % kXcd, q = nb / kXcd, r = nb % kXcd;
+  return x * q + min(x, r) + b / kXcd;
+}
+
 // ---------------------------------------------------------------------------
 // Unrolled tensor-product gather / scatter over the innermost dimensions
 // p..D-1 of a patch with strides st[] (last stride 1). Gather is sum-factorised
@@ -188,9 +200,11 @@ struct Group {
   static constexpr int V = (D == 1) ? 4 : 16;                      // coefficients per lane
   static constexpr int Q = (D <= 2) ? 16 : (D == 3 ? 8 : (D == 4 ? 16 : 32));   // points per item
   static constexpr int NG = kBlock / L;                            // groups per workgroup
+  static constexpr int PPB = kMaxPointsPerBlock[D];                // points per workgroup, at most
+  static constexpr int MAXI = PPB / Q + 256;                       // items per tile segment, at most
+  static constexpr bool STAGE_C = D <= 4;                          // coefficient patch in LDS
 };
 constexpr int kMaxTileCells = 256;
-constexpr int kMaxItems = 2048 / 8 + kMaxTileCells;   // ppb <= 2048 points, Q >= 8
 
 // Polynomial coefficients (t^0..t^3) of the cubic piece b_a on one interval.
 template <typename T>
@@ -201,11 +215,97 @@ __device__ __forceinline__ void piece_coeffs(int a, T& c0, T& c1, T& c2, T& c3) 
   else { c0 = T(0.0); c1 = T(0.0); c2 = T(0.0); c3 = T(1.0 / 6.0); }
 }
 
+// Cross-lane moves inside a quad / a row of 16 lanes (DPP, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRowRor4 = 0x124;   // row_ror:4
+constexpr int kDppRowRor8 = 0x128;   // row_ror:8
+
+// Sum over the L consecutive lanes of a group (L = 1, 4, 16 or 64); every
+// lane of the group gets the total.
 template <typename T, int L>
 __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-  for (int o = 1; o < L; o <<= 1) v += __shfl_xor(v, o);
+  if constexpr (L >= 4) {
+    v += dpp_mov<kDppQuadXor1>(v);
+    v += dpp_mov<kDppQuadXor2>(v);
+  }
+  if constexpr (L >= 16) {
+    v += dpp_mov<kDppRowRor4>(v);
+    v += dpp_mov<kDppRowRor8>(v);
+  }
+  if constexpr (L >= 64) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+  }
   return v;
+}
+
+// Per-point values of one lane: its factor of the leading dimensions (w) and
+// the four cubic values of the last two dimensions (bm2, bm1).
+template <int D, typename T>
+struct PointVals {
+  T w;
+  T bm1[4];
+  T bm2[4];
+};
+
+template <int D, typename T, int NLEAD, int PPB>
+__device__ __forceinline__ void point_basis(const T (&s_tt)[D][PPB], int li, const T (&hc)[NLEAD > 0 ? NLEAD : 1][4],
+                                            PointVals<D, T>& q) {
+  T tt[D];
+#pragma unroll
+  for (int p = 0; p < D; ++p) tt[p] = s_tt[p][li];
+  q.w = T(1);
+#pragma unroll
+  for (int k = 0; k < NLEAD; ++k) q.w *= ((hc[k][3] * tt[k] + hc[k][2]) * tt[k] + hc[k][1]) * tt[k] + hc[k][0];
+  cubic_basis(tt[D - 1], q.bm1);
+  if constexpr (D >= 2) cubic_basis(tt[D - 2], q.bm2);
+}
+
+// The lane's share of v'c (before the factor w): sum over its 16 (or 4) entries.
+template <int D, typename T, int V>
+__device__ __forceinline__ T point_gather(const PointVals<D, T>& q, const T (&cv)[V]) {
+  T tl = T(0);
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) tl += q.bm1[b] * cv[b];
+  } else {
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa) {
+      T r = T(0);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) r += q.bm1[b] * cv[aa * 4 + b];
+      tl += q.bm2[aa] * r;
+    }
+  }
+  return tl;
+}
+
+// acc += s v (or s v.^2 for the diagonal) over the lane's entries.
+template <int D, typename T, bool SQ, int V>
+__device__ __forceinline__ void point_scatter(const PointVals<D, T>& q, T s, T (&acc)[V]) {
+  const T u = SQ ? s * q.w * q.w : s * q.w;
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] += SQ ? u * q.bm1[b] * q.bm1[b] : u * q.bm1[b];
+  } else {
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa) {
+      const T ua = SQ ? u * q.bm2[aa] * q.bm2[aa] : u * q.bm2[aa];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[aa * 4 + b] += SQ ? ua * q.bm1[b] * q.bm1[b] : ua * q.bm1[b];
+    }
+  }
 }
 
 template <int D, typename T, int MODE>
@@ -215,11 +315,15 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   constexpr int V = GP::V;
   constexpr int Q = GP::Q;
   constexpr int NLEAD = (D >= 3) ? D - 2 : 0;       // dimensions owned by the lane index
+  constexpr int PPB = GP::PPB;
+  constexpr int MAXI = GP::MAXI;
+  constexpr bool STAGE_C = GP::STAGE_C;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int it_cell[kMaxItems];
-  __shared__ int it_lo[kMaxItems];
-  __shared__ int it_cnt[kMaxItems];
+  __shared__ int it_cell[MAXI];
+  __shared__ int it_lo[MAXI];
+  __shared__ int it_cnt[MAXI];
   __shared__ int scan_sh[kBlock / 64];
+  __shared__ T s_tt[D][PPB];   // level-g position of each point of the segment in its cell
 
   T* lc = reinterpret_cast<T*>(smem_raw);
   const int Tg = 1 << a.tb;
@@ -227,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   int patch = 1;
 #pragma unroll
   for (int p = 0; p < D; ++p) patch *= P;
-  T* lacc = (MODE == kApply) ? lc + patch : lc;
+  T* lacc = (MODE == kApply && STAGE_C) ? lc + patch : lc;
 
   int st[D];
   st[D - 1] = 1;
@@ -257,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     lead_off += aq * st[q];
   }
 
-  int64_t pos = int64_t(blockIdx.x) * a.ppb;
+  int64_t pos = int64_t(xcd_block()) * a.ppb;
   const int64_t end = min(a.n, pos + int64_t(a.ppb));
   while (pos < end) {
     const uint32_t tile = a.mkey[pos] >> S;
@@ -280,9 +384,20 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       lo_rel = int(lo - pos);
       nch = (cnt + Q - 1) / Q;
     }
-    // stage the coefficient patch, clear the accumulator
+    // stage the segment's points (one coalesced pass) ...
+    const int mseg = int(seg_end - pos);
+    for (int idx = threadIdx.x; idx < mseg; idx += kBlock) {
+      const size_t i = size_t(pos) + size_t(idx);
+      const uint32_t cf = a.cell[i];
+#pragma unroll
+      for (int p = 0; p < D; ++p) {
+        const uint32_t cfp = (cf >> (a.G * (D - 1 - p))) & maskN;
+        s_tt[p][idx] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + i]) * scale;
+      }
+    }
+    // ... and the coefficient patch; clear the accumulator
     for (int e = threadIdx.x; e < patch; e += kBlock) {
-      if constexpr (MODE == kApply) {
+      if constexpr (MODE == kApply && STAGE_C) {
         int rem = e;
         int64_t gidx = 0;
 #pragma unroll
@@ -297,14 +412,14 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     }
     int n_items_all;
     const int first = block_exclusive_scan(nch, scan_sh, &n_items_all);
-    // first + k < ppb / Q + kMaxTileCells <= kMaxItems (the host caps ppb at 2048)
-    for (int k = 0; k < nch && first + k < kMaxItems; ++k) {
+    // first + k < PPB / Q + kMaxTileCells = MAXI (the host keeps ppb <= PPB)
+    for (int k = 0; k < nch && first + k < MAXI; ++k) {
       it_cell[first + k] = int(threadIdx.x);
       it_lo[first + k] = lo_rel + k * Q;
       it_cnt[first + k] = min(Q, cnt - k * Q);
     }
     __syncthreads();
-    const int n_items = min(n_items_all, kMaxItems);
+    const int n_items = min(n_items_all, MAXI);
 
     for (int it = grp; it < n_items; it += GP::NG) {
       const int j = it_cell[it];
@@ -316,77 +431,58 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       int sa = 0;
       if constexpr (D >= 2) sa = st[D - 2];
       T cv[V], acc[V];
+      if constexpr (MODE == kApply && !STAGE_C) {
+        // global index of the lane's first coefficient: tile origin + local offset
+        int64_t gbase = 0;
+        int rem = base;
+#pragma unroll
+        for (int p = 0; p < D; ++p) {
+          const int l = rem / st[p];
+          rem -= l * st[p];
+          gbase = gbase * Jg + (org[p] + l);
+        }
+        const int64_t gsa = (D >= 2) ? int64_t(Jg) : 0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) cv[v] = cin[gbase + (D == 1 ? v : (v >> 2) * gsa + (v & 3))];
+      }
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const int off = (D == 1) ? v : ((v >> 2) * sa + (v & 3));
-        if constexpr (MODE == kApply) cv[v] = lc[base + off];
+        if constexpr (MODE == kApply && STAGE_C) cv[v] = lc[base + off];
         acc[v] = T(0);
       }
-      const int64_t i0 = pos + it_lo[it];
-      const int64_t i1 = i0 + it_cnt[it];
-      for (int64_t i = i0; i < i1; ++i) {
-        const uint32_t cf = a.cell[i];
-        T tt[D];
-#pragma unroll
-        for (int p = 0; p < D; ++p) {
-          const uint32_t cfp = (cf >> (a.G * (D - 1 - p))) & maskN;
-          tt[p] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + size_t(i)]) * scale;
-        }
-        // the lane's factor of the leading dimensions
-        T w = T(1);
-#pragma unroll
-        for (int q = 0; q < NLEAD; ++q) w *= ((hc[q][3] * tt[q] + hc[q][2]) * tt[q] + hc[q][1]) * tt[q] + hc[q][0];
-        T bm1[4], bm2[4];
-        cubic_basis(tt[D - 1], bm1);
-        if constexpr (D >= 2) cubic_basis(tt[D - 2], bm2);
-        T s;
+      const int l0 = it_lo[it];
+      const int l1 = l0 + it_cnt[it];
+      // two points per step: independent chains for the scheduler to interleave
+      int li = l0;
+      for (; li + 1 < l1; li += 2) {
+        PointVals<D, T> q0, q1;
+        point_basis<D, T, NLEAD>(s_tt, li, hc, q0);
+        point_basis<D, T, NLEAD>(s_tt, li + 1, hc, q1);
+        T s0, s1;
         if constexpr (MODE == kApply) {
-          T tl = T(0);
-          if constexpr (D == 1) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) tl += bm1[b] * cv[b];
-          } else {
-#pragma unroll
-            for (int aa = 0; aa < 4; ++aa) {
-              T r = T(0);
-#pragma unroll
-              for (int b = 0; b < 4; ++b) r += bm1[b] * cv[aa * 4 + b];
-              tl += bm2[aa] * r;
-            }
-          }
-          s = group_sum<T, L>(w * tl);
+          const T g0 = q0.w * point_gather<D, T>(q0, cv);
+          const T g1 = q1.w * point_gather<D, T>(q1, cv);
+          s0 = group_sum<T, L>(g0);
+          s1 = group_sum<T, L>(g1);
         } else if constexpr (MODE == kRhs) {
-          s = T(a.y[i]);
+          s0 = T(a.y[pos + li]);
+          s1 = T(a.y[pos + li + 1]);
         } else {
-          s = T(1);
+          s0 = T(1);
+          s1 = T(1);
         }
-        if constexpr (MODE == kDiag) {
-          const T u = s * w * w;
-          if constexpr (D == 1) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[b] += u * bm1[b] * bm1[b];
-          } else {
-#pragma unroll
-            for (int aa = 0; aa < 4; ++aa) {
-              const T ua = u * bm2[aa] * bm2[aa];
-#pragma unroll
-              for (int b = 0; b < 4; ++b) acc[aa * 4 + b] += ua * bm1[b] * bm1[b];
-            }
-          }
-        } else {
-          const T u = s * w;
-          if constexpr (D == 1) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[b] += u * bm1[b];
-          } else {
-#pragma unroll
-            for (int aa = 0; aa < 4; ++aa) {
-              const T ua = u * bm2[aa];
-#pragma unroll
-              for (int b = 0; b < 4; ++b) acc[aa * 4 + b] += ua * bm1[b];
-            }
-          }
-        }
+        point_scatter<D, T, MODE == kDiag>(q0, s0, acc);
+        point_scatter<D, T, MODE == kDiag>(q1, s1, acc);
+      }
+      if (li < l1) {
+        PointVals<D, T> q0;
+        point_basis<D, T, NLEAD>(s_tt, li, hc, q0);
+        T s0;
+        if constexpr (MODE == kApply) s0 = group_sum<T, L>(q0.w * point_gather<D, T>(q0, cv));
+        else if constexpr (MODE == kRhs) s0 = T(a.y[pos + li]);
+        else s0 = T(1);
+        point_scatter<D, T, MODE == kDiag>(q0, s0, acc);
       }
 #pragma unroll
       for (int v = 0; v < V; ++v) {
@@ -988,6 +1084,206 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double* A, int K, const T
 }
 
 // ---------------------------------------------------------------------------
+// Assembled operator of a coarse level as a 7^D-point stencil.
+//
+// On level g every cell's data Gram block is a linear function of the cell's
+// polynomial moments M[c][e] = sum_i prod_p u_ip^e_p (u = level-g position
+// in the cell minus 1/2, e_p = 0..6), so the data part of A_g[k, k+o] is
+//   sum_c sum_e M[c][e] prod_p C[e_p][k_p - c_p][k_p + o_p - c_p]
+// with the 7x4x4 table C of u^e coefficients of b_a(u+1/2) b_a'(u+1/2).
+// Per dimension this is one and the same (7J) x (7N) matrix W acting on the
+// axis (c_p, e_p), so the whole stencil is (W x ... x W) M: D banded passes
+// (the Kronecker matvec of Alg. 2). lambda Lambda_g is added from the banded
+// 1D factors; the result is stored offset-major, S[o][k].
+
+// Moments of level g, written to the axis-interleaved layout
+// index = sum_p (c_p * 7 + e_p) * (7 N_g)^(D-1-p). Block (x, y): exponent
+// tuples (e_1..e_{D-1}) = x * kBlock + tid (all seven e_0), level-g cell y
+// in Morton order.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_level_moments(const double* t64, const uint32_t* cell,
+                                                          const int32_t* off, int64_t n, int G, int g,
+                                                          double* mom) {
+  constexpr int E = 7;
+  constexpr int TILE = 64;
+  __shared__ double pw[TILE][D][E];
+  int nrest = 1;
+#pragma unroll
+  for (int p = 1; p < D; ++p) nrest *= E;
+  const int sh = G - g;
+  const int S = D * sh;
+  const uint32_t ncells = 1u << (D * g);
+  const int r = blockIdx.x * kBlock + threadIdx.x;
+  for (uint32_t cidx = blockIdx.y; cidx < ncells; cidx += gridDim.y) {
+  const int64_t c0 = off[size_t(cidx) << S], c1 = off[size_t(cidx + 1) << S];
+  int er[D];
+  {
+    int rem = r;
+#pragma unroll
+    for (int p = D - 1; p >= 1; --p) { er[p] = rem % E; rem /= E; }
+    er[0] = 0;
+  }
+  const uint32_t maskN = (1u << G) - 1u, maskSh = (1u << sh) - 1u;
+  const double scale = 1.0 / double(1u << sh);
+  double acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0.0;
+  __syncthreads();   // the previous cell's readers of pw are done
+  for (int64_t base = c0; base < c1; base += TILE) {
+    __syncthreads();
+    for (int w = threadIdx.x; w < TILE * D; w += kBlock) {
+      const int pt = w / D, p = w % D;
+      const int64_t i = base + pt;
+      double u = 0.0;
+      const bool ok = i < c1;
+      if (ok) {
+        const uint32_t cfp = (cell[i] >> (G * (D - 1 - p))) & maskN;
+        u = (double(cfp & maskSh) + t64[size_t(p) * n + i]) * scale - 0.5;
+      }
+      double v = ok ? 1.0 : 0.0;
+      for (int e = 0; e < E; ++e) { pw[pt][p][e] = v; v *= u; }
+    }
+    __syncthreads();
+    if (r < nrest) {
+      const int cnt = int(min(int64_t(TILE), c1 - base));
+      for (int pt = 0; pt < cnt; ++pt) {
+        double prod = 1.0;
+#pragma unroll
+        for (int p = 1; p < D; ++p) prod *= pw[pt][p][er[p]];
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] += prod * pw[pt][0][e];
+      }
+    }
+  }
+  if (r < nrest) {
+    int cc[D];
+    morton_decode<D>(cidx, g, cc);
+    const int64_t A = int64_t(E) << g;   // 7 N_g
+    int64_t idx_rest = 0;
+#pragma unroll
+    for (int p = 1; p < D; ++p) idx_rest = idx_rest * A + (int64_t(cc[p]) * E + er[p]);
+    int64_t strideA0 = 1;
+#pragma unroll
+    for (int p = 1; p < D; ++p) strideA0 *= A;
+#pragma unroll
+    for (int e = 0; e < E; ++e) mom[(int64_t(cc[0]) * E + e) * strideA0 + idx_rest] = acc[e];
+  }
+  }   // cells
+}
+
+// One Kronecker pass: axis p goes from (c, e) (size 7N) to (k, o+3) (size 7J).
+// in [outer][7N][inner] -> out [outer][7J][inner].
+__global__ __launch_bounds__(kBlock) void k_stencil_pass(const double* in, double* out, const double* ctab,
+                                                         int N, int64_t inner, int64_t total) {
+  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= total) return;
+  const int J = N + kDeg;
+  const int64_t ii = t % inner;
+  const int64_t rest = t / inner;
+  const int ko = int(rest % (7 * J));
+  const int64_t outer = rest / (7 * J);
+  const int k = ko / 7, o = ko % 7 - 3;
+  const int l = k + o;
+  double sacc = 0.0;
+  if (l >= 0 && l < J) {
+    const int clo = max(0, max(k, l) - 3), chi = min(N - 1, min(k, l));
+    const int64_t ibase = outer * (int64_t(7) * N) * inner + ii;
+    for (int c = clo; c <= chi; ++c) {
+      const int pi = (k - c) * 4 + (l - c);
+#pragma unroll
+      for (int e = 0; e < 7; ++e) sacc += ctab[e * 16 + pi] * in[ibase + (int64_t(c) * 7 + e) * inner];
+    }
+  }
+  out[t] = sacc;
+}
+
+// S[o][k] = (data stencil in the interleaved layout) + lambda Lambda_g[k, k+o];
+// entries whose neighbour falls outside the grid are zero.
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_stencil_finalize(const double* inter, const double* band, int J,
+                                                             int64_t K, double lam, double* S64, float* S32) {
+  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  int NO = 1;
+#pragma unroll
+  for (int p = 0; p < D; ++p) NO *= 7;
+  if (t >= int64_t(NO) * K) return;
+  const int oidx = int(t / K);
+  const int64_t k = t % K;
+  int kp[D], op[D];
+  {
+    int64_t rk = k;
+    int ro = oidx;
+#pragma unroll
+    for (int p = D - 1; p >= 0; --p) {
+      kp[p] = int(rk % J); rk /= J;
+      op[p] = ro % 7; ro /= 7;
+    }
+  }
+  bool inside = true;
+  int64_t ii = 0;
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    const int l = kp[p] + op[p] - 3;
+    inside = inside && l >= 0 && l < J;
+    ii = ii * (int64_t(7) * J) + (int64_t(kp[p]) * 7 + op[p]);
+  }
+  double v = 0.0;
+  if (inside) {
+    double mv[D], g1v[D], g2v[D];
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      const double* bp = band + size_t(p) * 3 * J * 7;
+      mv[p] = bp[size_t(kp[p]) * 7 + op[p]];
+      g1v[p] = bp[size_t(J) * 7 + size_t(kp[p]) * 7 + op[p]];
+      g2v[p] = bp[size_t(2 * J) * 7 + size_t(kp[p]) * 7 + op[p]];
+    }
+    double lm = 0.0;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      double w = g2v[p];
+#pragma unroll
+      for (int q = 0; q < D; ++q)
+        if (q != p) w *= mv[q];
+      lm += w;
+    }
+#pragma unroll
+    for (int p = 0; p < D; ++p)
+#pragma unroll
+      for (int q = p + 1; q < D; ++q) {
+        double w = 2.0 * g1v[p] * g1v[q];
+#pragma unroll
+        for (int r = 0; r < D; ++r)
+          if (r != p && r != q) w *= mv[r];
+        lm += w;
+      }
+    v = inter[ii] + lam * lm;
+  }
+  S64[t] = v;
+  S32[t] = float(v);
+}
+
+// out = A_g c with the stored stencil: out[k] = sum_o S[o][k] c[k + off(o)].
+// A neighbour outside the grid has S = 0; its index is clamped into range so
+// the (finite) value read there is multiplied by zero.
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int32_t* offs, const T* c, T* out,
+                                                          int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  int NO = 1;
+#pragma unroll
+  for (int p = 0; p < D; ++p) NO *= 7;
+  T acc = T(0);
+#pragma unroll 7
+  for (int o = 0; o < NO; ++o) {
+    int64_t j = k + offs[o];
+    j = j < 0 ? 0 : (j >= K ? K - 1 : j);
+    acc += S[int64_t(o) * K + k] * c[j];
+  }
+  out[k] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers.
 static inline unsigned blocks_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
@@ -996,7 +1292,8 @@ static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
   const int Tg = 1 << a.tb;
   int patch = 1;
   for (int p = 0; p < D; ++p) patch *= (Tg + kDeg);
-  const size_t lds = size_t(patch) * sizeof(T) * (MODE == kApply ? 2 : 1);
+  const size_t lds = size_t(patch) * sizeof(T) * ((MODE == kApply && Group<D>::STAGE_C) ? 2 : 1);
+  if (a.ppb > Group<D>::PPB) return hipErrorInvalidValue;
   const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
   if (grid == 0) return hipSuccess;
   if (lds > 65536) {
@@ -1289,5 +1586,64 @@ template hipError_t launch_gemv<float, double, double>(const double*, int, const
                                                        double*, hipStream_t);
 template hipError_t launch_gemv<double, double, float>(const double*, int, const double*, double, const double*,
                                                        float*, hipStream_t);
+
+hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n,
+                                int G, int g, double* mom, hipStream_t st) {
+  int nrest = 1;
+  for (int p = 1; p < D; ++p) nrest *= 7;
+  const unsigned ncells = 1u << (D * g);
+  const dim3 grid(unsigned((nrest + kBlock - 1) / kBlock), ncells < 32768u ? ncells : 32768u);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_level_moments<1>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
+    case 2: hipLaunchKernelGGL(k_level_moments<2>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
+    case 3: hipLaunchKernelGGL(k_level_moments<3>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
+    case 4: hipLaunchKernelGGL(k_level_moments<4>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
+    case 5: hipLaunchKernelGGL(k_level_moments<5>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_pass(const double* in, double* out, const double* ctab, int N, int64_t outer,
+                               int64_t inner, hipStream_t st) {
+  const int64_t total = outer * int64_t(7) * (N + kDeg) * inner;
+  hipLaunchKernelGGL(k_stencil_pass, dim3(blocks_for(total)), dim3(kBlock), 0, st, in, out, ctab, N, inner, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil_finalize(int D, const double* inter, const double* band, int J, int64_t K, double lam,
+                                   double* S64, float* S32, hipStream_t st) {
+  int64_t NO = 1;
+  for (int p = 0; p < D; ++p) NO *= 7;
+  const unsigned g = blocks_for(NO * K);
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_stencil_finalize<1>, dim3(g), dim3(kBlock), 0, st, inter, band, J, K, lam, S64, S32); break;
+    case 2: hipLaunchKernelGGL(k_stencil_finalize<2>, dim3(g), dim3(kBlock), 0, st, inter, band, J, K, lam, S64, S32); break;
+    case 3: hipLaunchKernelGGL(k_stencil_finalize<3>, dim3(g), dim3(kBlock), 0, st, inter, band, J, K, lam, S64, S32); break;
+    case 4: hipLaunchKernelGGL(k_stencil_finalize<4>, dim3(g), dim3(kBlock), 0, st, inter, band, J, K, lam, S64, S32); break;
+    case 5: hipLaunchKernelGGL(k_stencil_finalize<5>, dim3(g), dim3(kBlock), 0, st, inter, band, J, K, lam, S64, S32); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stencil_apply(int D, const T* S, const int32_t* offs, const T* c, T* out, int64_t K,
+                                hipStream_t st) {
+  const unsigned g = blocks_for(K);
+  switch (D) {
+    case 1: hipLaunchKernelGGL((k_stencil_apply<T, 1>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
+    case 2: hipLaunchKernelGGL((k_stencil_apply<T, 2>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
+    case 3: hipLaunchKernelGGL((k_stencil_apply<T, 3>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
+    case 4: hipLaunchKernelGGL((k_stencil_apply<T, 4>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
+    case 5: hipLaunchKernelGGL((k_stencil_apply<T, 5>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_stencil_apply<double>(int, const double*, const int32_t*, const double*, double*, int64_t,
+                                                 hipStream_t);
+template hipError_t launch_stencil_apply<float>(int, const float*, const int32_t*, const float*, float*, int64_t,
+                                                hipStream_t);
 
 }  // namespace tsmg

@@ -89,6 +89,17 @@ hipError_t launch_symmetrize(double* A, int K, hipStream_t st);
 template <typename TB, typename TV, typename TO>
 hipError_t launch_gemv(const double* A, int K, const TB* base, double s, const TV* v, TO* out, hipStream_t st);
 
+// Assembled 7^D stencil of a level (moments -> D Kronecker passes -> finalize).
+hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n,
+                                int G, int g, double* mom, hipStream_t st);
+hipError_t launch_stencil_pass(const double* in, double* out, const double* ctab, int N, int64_t outer,
+                               int64_t inner, hipStream_t st);
+hipError_t launch_stencil_finalize(int D, const double* inter, const double* band, int J, int64_t K, double lam,
+                                   double* S64, float* S32, hipStream_t st);
+template <typename T>
+hipError_t launch_stencil_apply(int D, const T* S, const int32_t* offs, const T* c, T* out, int64_t K,
+                                hipStream_t st);
+
 // Radix sort of (key, index) pairs on the low `bits` bits (sort.hip).
 hipError_t sort_pairs(uint32_t* key_in, uint32_t* key_out, uint32_t* val_in, uint32_t* val_out, int64_t n,
                       int bits, void* tmp, size_t* tmp_bytes, hipStream_t st);

@@ -192,9 +192,20 @@ static DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out
   return a;
 }
 
-// out = A_g c (Sec. 2.4): Lambda passes write out, the point pass adds Phi'Phi c.
+template <typename T> static const T* lvl_S(Level& L);
+template <> const double* lvl_S<double>(Level& L) { return L.S64.p; }
+template <> const float* lvl_S<float>(Level& L) { return L.S32.p; }
+
+// out = A_g c (Sec. 2.4): Lambda passes write out, the point pass adds
+// Phi'Phi c; or, on a level assembled at setup, one stencil product.
 template <typename T>
 void apply_op(Problem* P, int g, const T* c, T* out) {
+  Level& L = P->lev[g];
+  if (L.stencil) {
+    hip_check(launch_stencil_apply<T>(P->d, lvl_S<T>(L), L.soffs.p, c, out, L.K, P->stream), "stencil apply");
+    P->applies++;
+    return;
+  }
   lambda_apply<T>(P, g, c, out);
   const bool fp32 = sizeof(T) == 4;
   hip_check(launch_data(P->d, fp32, kApply, data_args(P, g, fp32, c, out), P->stream), "data pass");
@@ -422,6 +433,75 @@ static double lanczos_theta(Problem* P, int g, int steps) {
   return tridiag_max_eig(al, be);
 }
 
+// Assembles A_g of level g as a 7^d-point stencil: level moments, d
+// Kronecker passes with the pair table, then lambda Lambda_g and the
+// offset-major layout.
+static void build_stencil(Problem* P, int g) {
+  Level& L = P->lev[g];
+  const int D = P->d, N = L.N, J = L.J;
+  int64_t NO = 1, in_sz = 1, max_sz = 0;
+  for (int p = 0; p < D; ++p) { NO *= 7; in_sz *= int64_t(7) * N; }
+  max_sz = in_sz;
+  {
+    int64_t sz = in_sz;
+    for (int p = 0; p < D; ++p) { sz = sz / (int64_t(7) * N) * (int64_t(7) * J); max_sz = std::max(max_sz, sz); }
+  }
+  DevBuf<double> bufA, bufB, ctab;
+  bufA.alloc(size_t(max_sz));
+  bufB.alloc(size_t(max_sz));
+  std::vector<double> ct;
+  pair_table(ct);
+  ctab.alloc(ct.size());
+  hip_check(hipMemcpyAsync(ctab.p, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, P->stream),
+            "upload");
+  hip_check(launch_level_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, g, bufA.p, P->stream), "moments");
+  double* cur = bufA.p;
+  double* nxt = bufB.p;
+  for (int p = 0; p < D; ++p) {
+    int64_t outer = 1, inner = 1;
+    for (int q = 0; q < p; ++q) outer *= int64_t(7) * J;
+    for (int q = p + 1; q < D; ++q) inner *= int64_t(7) * N;
+    hip_check(launch_stencil_pass(cur, nxt, ctab.p, N, outer, inner, P->stream), "stencil pass");
+    std::swap(cur, nxt);
+  }
+  L.S64.alloc(size_t(NO * L.K));
+  L.S32.alloc(size_t(NO * L.K));
+  hip_check(launch_stencil_finalize(D, cur, L.band64.p, J, L.K, P->lam, L.S64.p, L.S32.p, P->stream), "finalize");
+  std::vector<int32_t> offs(static_cast<size_t>(NO));
+  for (int64_t o = 0; o < NO; ++o) {
+    int64_t rem = o, off = 0, stride = 1;
+    for (int p = D - 1; p >= 0; --p) {
+      off += (rem % 7 - 3) * stride;
+      rem /= 7;
+      stride *= J;
+    }
+    offs[size_t(o)] = int32_t(off);
+  }
+  L.soffs.alloc(offs.size());
+  hip_check(hipMemcpyAsync(L.soffs.p, offs.data(), offs.size() * sizeof(int32_t), hipMemcpyHostToDevice, P->stream),
+            "upload");
+  hip_check(hipStreamSynchronize(P->stream), "sync");   // temporaries and host tables go out of scope
+  L.stencil = true;
+}
+
+// Which levels get an assembled stencil: it must fit the memory budget and,
+// in automatic mode, its estimated time (a stream of 8 bytes per entry at
+// about 5 TB/s) must beat the point pass (about 0.5 ps per point and patch
+// entry, as measured for the FP64 point pass on MI355X).
+static bool want_stencil(const Problem* P, const Level& L, size_t free_bytes) {
+  if (P->opt.stencil_mode == 1) return false;
+  double NO = 1.0, P4 = 1.0;
+  for (int p = 0; p < P->d; ++p) { NO *= 7.0; P4 *= 4.0; }
+  const double entries = NO * double(L.K);
+  double transient = 1.0;
+  for (int p = 0; p < P->d; ++p) transient *= 7.0 * L.J;
+  const double bytes = entries * 12.0 + 2.0 * transient * 8.0;
+  const double budget = std::min(16e9, 0.4 * double(free_bytes));
+  if (bytes > budget) return false;
+  if (P->opt.stencil_mode == 2) return true;
+  return entries * 1.6e-12 < double(P->n) * P4 * 0.5e-12;
+}
+
 // A_1 = sum over level-1 cells of the cell Gram (from moments) + lambda
 // Lambda_1, then its inverse by Gauss-Jordan; pivots checked for positivity.
 static void build_coarse(Problem* P) {
@@ -585,13 +665,14 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     }
 
     // --- data-term work split
-    // (the point pass sizes its item lists for at most 2048 points per workgroup)
+    // (the point pass stages at most kMaxPointsPerBlock[d] points per workgroup)
+    const int ppb_max = kMaxPointsPerBlock[d];
     if (P->opt.points_per_block > 0) {
-      P->ppb = std::max(64, std::min(2048, P->opt.points_per_block));
+      P->ppb = std::max(64, std::min(ppb_max, P->opt.points_per_block));
     } else {
       int64_t ppb = (n + 4095) / 4096;
       ppb = ((ppb + 63) / 64) * 64;
-      P->ppb = int(std::max<int64_t>(256, std::min<int64_t>(2048, ppb)));
+      P->ppb = int(std::max<int64_t>(std::min(256, ppb_max), std::min<int64_t>(ppb_max, ppb)));
     }
 
     // --- levels g = 1..G (N_g = 2^g)
@@ -641,6 +722,14 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     P->p32.alloc(size_t(KG));
     P->v32.alloc(size_t(KG));
     P->d32.alloc(size_t(KG));
+
+    // --- assembled stencils for the levels where they pay (same A_g)
+    {
+      size_t free_b = 0, total_b = 0;
+      hip_check(hipMemGetInfo(&free_b, &total_b), "meminfo");
+      for (int g = 1; g <= G; ++g)
+        if (want_stencil(P, P->lev[g], free_b)) build_stencil(P, g);
+    }
 
     // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)
     for (int g = 1; g <= G; ++g) compute_diag(P, g);

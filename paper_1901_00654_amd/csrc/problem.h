@@ -63,6 +63,10 @@ struct Level {
   DevBuf<float> wdinv32;
   DevBuf<double> a64, b64, t64;    // V-cycle iterate, right-hand side, A x work vector
   DevBuf<float> a32, b32, t32;
+  bool stencil = false;            // A_g assembled as a 7^d-point stencil
+  DevBuf<double> S64;              // [7^d][K] offset-major stencil
+  DevBuf<float> S32;
+  DevBuf<int32_t> soffs;           // [7^d] flat index offset of each stencil point
 };
 
 constexpr int kSlots = 16;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libtsmg.so")
 
 TS_OK, TS_ENOTCONV, TS_EINVAL, TS_ENOMEM, TS_EDEVICE, TS_ESINGULAR, TS_EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
 TS_FP64, TS_MIXED_FP32, TS_MIXED_BF16 = 0, 1, 2
+TS_STENCIL_AUTO, TS_STENCIL_NONE, TS_STENCIL_ALL = 0, 1, 2
 _STATUS = {0: "TS_OK", 1: "TS_ENOTCONV", -1: "TS_EINVAL", -2: "TS_ENOMEM", -3: "TS_EDEVICE",
            -4: "TS_ESINGULAR", -5: "TS_EBREAKDOWN"}
 
@@ -28,7 +29,8 @@ class ts_options(ctypes.Structure):
                 ("omega_fixed", ctypes.c_double), ("precision", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
-                ("points_per_block", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("points_per_block", ctypes.c_int), ("stencil_mode", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class ts_solve_info(ctypes.Structure):

@@ -45,6 +45,26 @@ def test_apply_fp64_every_level(prob):
         assert gc.rel(out, gc.oracle_apply(w, Ng, c)) < 1e-12, g
 
 
+@pytest.mark.parametrize("mode", [tsmg.TS_STENCIL_NONE, tsmg.TS_STENCIL_ALL])
+def test_apply_every_level_matrix_free_and_stencil(prob, mode):
+    """Both ways of applying A_g (point pass + Lambda passes, or the stencil
+    assembled at setup) against the oracle on every level, FP64 and FP32."""
+    w, _ = prob
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"], stencil_mode=mode)
+    try:
+        rng = np.random.default_rng(105)
+        for g in levels(S):
+            Ng = w["N"] >> (S.G - g)
+            c = rng.standard_normal(S.K(g))
+            ref = gc.oracle_apply(w, Ng, c)
+            assert gc.rel(S.apply(g, c).cpu().numpy(), ref) < 1e-12, (mode, g)
+            c32 = c.astype(np.float32)
+            ref32 = gc.oracle_apply(w, Ng, c32.astype(np.float64))
+            assert gc.rel(S.apply(g, c32, fp32=True).cpu().numpy(), ref32) < 3e-5, (mode, g)
+    finally:
+        S.close()
+
+
 def test_apply_fp32_finest_and_coarsest(prob):
     w, S = prob
     rng = np.random.default_rng(101)

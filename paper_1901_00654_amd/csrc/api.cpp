@@ -206,7 +206,7 @@ ts_status ts_restrict(ts_problem* p, int level, const double* r, double* out) {
   Problem* P = get(p);
   check_level(P, level, 2);
   need(r && out, "r and out must not be null");
-  tsmg::restrict_op<double>(P, level, r, out);
+  tsmg::restrict_op<double>(P, level, r, out, static_cast<const double*>(nullptr));
   return TS_OK;
   TS_API_END
 }

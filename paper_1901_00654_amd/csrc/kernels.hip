@@ -11,6 +11,8 @@
 // (Sec. 3.2.4); CG vector kernels with device-resident scalars (Alg. 8).
 // Setup: binning, offsets, Jacobi diagonal (Alg. 5 + Kronecker diagonal),
 // coarse assembly by polynomial moments, Gauss-Jordan inversion.
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -640,7 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict_pass(TransferArgs<T> a) {
 #pragma unroll
   for (int m = 0; m < 5; ++m) {
     const int i = 2 * j - 3 + m;
-    if (i >= 0 && i < a.Jf) v += w[m] * a.in[ibase + int64_t(i) * inner];
+    if (i >= 0 && i < a.Jf) {
+      const int64_t idx = ibase + int64_t(i) * inner;
+      v += w[m] * (a.sub ? a.in[idx] - a.sub[idx] : a.in[idx]);
+    }
   }
   a.out[k] = v;
 }
@@ -1096,26 +1101,28 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double* A, int K, const T
 // (the Kronecker matvec of Alg. 2). lambda Lambda_g is added from the banded
 // 1D factors; the result is stored offset-major, S[o][k].
 
-// Moments of level g, written to the axis-interleaved layout
-// index = sum_p (c_p * 7 + e_p) * (7 N_g)^(D-1-p). Block (x, y): exponent
-// tuples (e_1..e_{D-1}) = x * kBlock + tid (all seven e_0), level-g cell y
-// in Morton order.
+// Moments of level g, accumulated (atomically; mom zeroed first) into the
+// axis-interleaved layout index = sum_p (c_p * 7 + e_p) * (7 N_g)^(D-1-p).
+// Block (x, y, z): exponent tuples (e_1..e_{D-1}) starting at x * NR, level-g
+// cells y, y + gridDim.y, ..., and the z-th of gridDim.z chunks of each
+// cell's points. Threads are (tuple, stream): the NS = kBlock / NR streams
+// take every NS-th point of a staged tile.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_level_moments(const double* t64, const uint32_t* cell,
                                                           const int32_t* off, int64_t n, int G, int g,
                                                           double* mom) {
   constexpr int E = 7;
   constexpr int TILE = 64;
+  constexpr int NREST = (D == 1) ? 1 : (D == 2 ? 7 : (D == 3 ? 49 : (D == 4 ? 343 : 2401)));
+  constexpr int NR = NREST < kBlock ? NREST : kBlock;   // tuples per block
+  constexpr int NS = kBlock / NR;                       // point streams per tuple
   __shared__ double pw[TILE][D][E];
-  int nrest = 1;
-#pragma unroll
-  for (int p = 1; p < D; ++p) nrest *= E;
   const int sh = G - g;
   const int S = D * sh;
   const uint32_t ncells = 1u << (D * g);
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  for (uint32_t cidx = blockIdx.y; cidx < ncells; cidx += gridDim.y) {
-  const int64_t c0 = off[size_t(cidx) << S], c1 = off[size_t(cidx + 1) << S];
+  const int tup = threadIdx.x % NR, strm = threadIdx.x / NR;
+  const int r = blockIdx.x * NR + tup;
+  const bool active = r < NREST && strm < NS;
   int er[D];
   {
     int rem = r;
@@ -1125,50 +1132,54 @@ __global__ __launch_bounds__(kBlock) void k_level_moments(const double* t64, con
   }
   const uint32_t maskN = (1u << G) - 1u, maskSh = (1u << sh) - 1u;
   const double scale = 1.0 / double(1u << sh);
-  double acc[E];
+  for (uint32_t cidx = blockIdx.y; cidx < ncells; cidx += gridDim.y) {
+    const int64_t c0 = off[size_t(cidx) << S], c1 = off[size_t(cidx + 1) << S];
+    const int64_t per = (c1 - c0 + gridDim.z - 1) / gridDim.z;
+    const int64_t b0 = c0 + int64_t(blockIdx.z) * per;
+    const int64_t b1 = min(c1, b0 + per);
+    double acc[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = 0.0;
-  __syncthreads();   // the previous cell's readers of pw are done
-  for (int64_t base = c0; base < c1; base += TILE) {
-    __syncthreads();
-    for (int w = threadIdx.x; w < TILE * D; w += kBlock) {
-      const int pt = w / D, p = w % D;
-      const int64_t i = base + pt;
-      double u = 0.0;
-      const bool ok = i < c1;
-      if (ok) {
-        const uint32_t cfp = (cell[i] >> (G * (D - 1 - p))) & maskN;
-        u = (double(cfp & maskSh) + t64[size_t(p) * n + i]) * scale - 0.5;
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+    for (int64_t base = b0; base < b1; base += TILE) {
+      __syncthreads();   // previous readers of pw are done
+      for (int w = threadIdx.x; w < TILE * D; w += kBlock) {
+        const int pt = w / D, p = w % D;
+        const int64_t i = base + pt;
+        double u = 0.0;
+        const bool ok = i < b1;
+        if (ok) {
+          const uint32_t cfp = (cell[i] >> (G * (D - 1 - p))) & maskN;
+          u = (double(cfp & maskSh) + t64[size_t(p) * n + i]) * scale - 0.5;
+        }
+        double v = ok ? 1.0 : 0.0;
+        for (int e = 0; e < E; ++e) { pw[pt][p][e] = v; v *= u; }
       }
-      double v = ok ? 1.0 : 0.0;
-      for (int e = 0; e < E; ++e) { pw[pt][p][e] = v; v *= u; }
+      __syncthreads();
+      if (active) {
+        const int cnt = int(min(int64_t(TILE), b1 - base));
+        for (int pt = strm; pt < cnt; pt += NS) {
+          double prod = 1.0;
+#pragma unroll
+          for (int p = 1; p < D; ++p) prod *= pw[pt][p][er[p]];
+#pragma unroll
+          for (int e = 0; e < E; ++e) acc[e] += prod * pw[pt][0][e];
+        }
+      }
     }
-    __syncthreads();
-    if (r < nrest) {
-      const int cnt = int(min(int64_t(TILE), c1 - base));
-      for (int pt = 0; pt < cnt; ++pt) {
-        double prod = 1.0;
+    if (active && b0 < b1) {
+      int cc[D];
+      morton_decode<D>(cidx, g, cc);
+      const int64_t A = int64_t(E) << g;   // 7 N_g
+      int64_t idx_rest = 0, strideA0 = 1;
 #pragma unroll
-        for (int p = 1; p < D; ++p) prod *= pw[pt][p][er[p]];
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] += prod * pw[pt][0][e];
+      for (int p = 1; p < D; ++p) {
+        idx_rest = idx_rest * A + (int64_t(cc[p]) * E + er[p]);
+        strideA0 *= A;
       }
+#pragma unroll
+      for (int e = 0; e < E; ++e) atomicAdd(&mom[(int64_t(cc[0]) * E + e) * strideA0 + idx_rest], acc[e]);
     }
   }
-  if (r < nrest) {
-    int cc[D];
-    morton_decode<D>(cidx, g, cc);
-    const int64_t A = int64_t(E) << g;   // 7 N_g
-    int64_t idx_rest = 0;
-#pragma unroll
-    for (int p = 1; p < D; ++p) idx_rest = idx_rest * A + (int64_t(cc[p]) * E + er[p]);
-    int64_t strideA0 = 1;
-#pragma unroll
-    for (int p = 1; p < D; ++p) strideA0 *= A;
-#pragma unroll
-    for (int e = 0; e < E; ++e) mom[(int64_t(cc[0]) * E + e) * strideA0 + idx_rest] = acc[e];
-  }
-  }   // cells
 }
 
 // One Kronecker pass: axis p goes from (c, e) (size 7N) to (k, o+3) (size 7J).
@@ -1262,25 +1273,55 @@ __global__ __launch_bounds__(kBlock) void k_stencil_finalize(const double* inter
   S32[t] = float(v);
 }
 
-// out = A_g c with the stored stencil: out[k] = sum_o S[o][k] c[k + off(o)].
-// A neighbour outside the grid has S = 0; its index is clamped into range so
-// the (finite) value read there is multiplied by zero.
-template <typename T, int D>
-__global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int32_t* offs, const T* c, T* out,
-                                                          int64_t K) {
-  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (k >= K) return;
-  int NO = 1;
-#pragma unroll
-  for (int p = 0; p < D; ++p) NO *= 7;
-  T acc = T(0);
-#pragma unroll 7
-  for (int o = 0; o < NO; ++o) {
-    int64_t j = k + offs[o];
-    j = j < 0 ? 0 : (j >= K ? K - 1 : j);
-    acc += S[int64_t(o) * K + k] * c[j];
+// v = A_g x with the stored stencil, v[k] = sum_o S[o][k] x[k + off(o)], then
+// the epilogue: out = v (kStPlain), out = x + w (b - v) (kStJacobi, one damped
+// Jacobi sweep of Alg. 6; out must not alias x), or out = v - b (kStResidual).
+// A block takes 36 rows; thread (plane, row) sums the 7^(D-1) stencil points
+// whose first-dimension offset is `plane`, and the 7 plane sums are added in
+// LDS. A neighbour outside the grid has S = 0; its index is clamped into range
+// so the (finite) value read there is multiplied by zero.
+enum StencilEpilogue : int { kStPlain = 0, kStJacobi = 1, kStResidual = 2 };
+constexpr int kStRows = kBlock / 7;   // 36 rows per block
+
+template <typename T, int D, int EPI>
+__global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int32_t* offs, const T* x, T* out,
+                                                          const T* b, const T* w, int64_t K) {
+  constexpr int NI = (D == 1) ? 1 : (D == 2 ? 7 : (D == 3 ? 49 : (D == 4 ? 343 : 2401)));
+  __shared__ T part[7][kStRows];
+  const int plane = threadIdx.x / kStRows;
+  const int rl = threadIdx.x % kStRows;
+  const int64_t k = int64_t(blockIdx.x) * kStRows + rl;
+  if (plane < 7) {
+    T a0 = T(0), a1 = T(0);
+    if (k < K) {
+      const int obase = plane * NI;
+      int j = 0;
+      for (; j + 1 < NI; j += 2) {
+        const int o0 = obase + j, o1 = o0 + 1;
+        int64_t i0 = k + offs[o0], i1 = k + offs[o1];
+        i0 = i0 < 0 ? 0 : (i0 >= K ? K - 1 : i0);
+        i1 = i1 < 0 ? 0 : (i1 >= K ? K - 1 : i1);
+        a0 += S[int64_t(o0) * K + k] * x[i0];
+        a1 += S[int64_t(o1) * K + k] * x[i1];
+      }
+      if (j < NI) {
+        const int o0 = obase + j;
+        int64_t i0 = k + offs[o0];
+        i0 = i0 < 0 ? 0 : (i0 >= K ? K - 1 : i0);
+        a0 += S[int64_t(o0) * K + k] * x[i0];
+      }
+    }
+    part[plane][rl] = a0 + a1;
   }
-  out[k] = acc;
+  __syncthreads();
+  if (threadIdx.x < kStRows && k < K) {
+    T v = T(0);
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v += part[q][threadIdx.x];
+    if constexpr (EPI == kStPlain) out[k] = v;
+    else if constexpr (EPI == kStJacobi) out[k] = x[k] + w[k] * (b[k] - v);
+    else out[k] = v - b[k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1591,8 +1632,15 @@ hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, 
                                 int G, int g, double* mom, hipStream_t st) {
   int nrest = 1;
   for (int p = 1; p < D; ++p) nrest *= 7;
+  const int nr = nrest < kBlock ? nrest : kBlock;
   const unsigned ncells = 1u << (D * g);
-  const dim3 grid(unsigned((nrest + kBlock - 1) / kBlock), ncells < 32768u ? ncells : 32768u);
+  const unsigned gy = ncells < 32768u ? ncells : 32768u;
+  // split each cell's points so that the grid holds a few thousand blocks
+  const unsigned gx = unsigned((nrest + nr - 1) / nr);
+  int64_t chunks = (4096 + int64_t(gx) * gy - 1) / (int64_t(gx) * gy);
+  const int64_t per_cell = n / int64_t(ncells) + 1;
+  chunks = std::max<int64_t>(1, std::min<int64_t>({chunks, 1024, (per_cell + 255) / 256}));
+  const dim3 grid(gx, gy, unsigned(chunks));
   switch (D) {
     case 1: hipLaunchKernelGGL(k_level_moments<1>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
     case 2: hipLaunchKernelGGL(k_level_moments<2>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
@@ -1627,23 +1675,32 @@ hipError_t launch_stencil_finalize(int D, const double* inter, const double* ban
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_stencil_apply(int D, const T* S, const int32_t* offs, const T* c, T* out, int64_t K,
-                                hipStream_t st) {
-  const unsigned g = blocks_for(K);
+template <typename T, int EPI>
+static hipError_t launch_stencil_epi(int D, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
+                                     const T* w, int64_t K, hipStream_t st) {
+  const unsigned g = unsigned((K + kStRows - 1) / kStRows);
   switch (D) {
-    case 1: hipLaunchKernelGGL((k_stencil_apply<T, 1>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
-    case 2: hipLaunchKernelGGL((k_stencil_apply<T, 2>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
-    case 3: hipLaunchKernelGGL((k_stencil_apply<T, 3>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
-    case 4: hipLaunchKernelGGL((k_stencil_apply<T, 4>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
-    case 5: hipLaunchKernelGGL((k_stencil_apply<T, 5>), dim3(g), dim3(kBlock), 0, st, S, offs, c, out, K); break;
+    case 1: hipLaunchKernelGGL((k_stencil_apply<T, 1, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+    case 2: hipLaunchKernelGGL((k_stencil_apply<T, 2, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+    case 3: hipLaunchKernelGGL((k_stencil_apply<T, 3, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+    case 4: hipLaunchKernelGGL((k_stencil_apply<T, 4, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+    case 5: hipLaunchKernelGGL((k_stencil_apply<T, 5, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
-template hipError_t launch_stencil_apply<double>(int, const double*, const int32_t*, const double*, double*, int64_t,
-                                                 hipStream_t);
-template hipError_t launch_stencil_apply<float>(int, const float*, const int32_t*, const float*, float*, int64_t,
-                                                hipStream_t);
+
+template <typename T>
+hipError_t launch_stencil_apply(int D, int epi, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
+                                const T* w, int64_t K, hipStream_t st) {
+  if (K == 0) return hipSuccess;
+  if (epi == kStPlain) return launch_stencil_epi<T, kStPlain>(D, S, offs, x, out, b, w, K, st);
+  if (epi == kStJacobi) return launch_stencil_epi<T, kStJacobi>(D, S, offs, x, out, b, w, K, st);
+  return launch_stencil_epi<T, kStResidual>(D, S, offs, x, out, b, w, K, st);
+}
+template hipError_t launch_stencil_apply<double>(int, int, const double*, const int32_t*, const double*, double*,
+                                                 const double*, const double*, int64_t, hipStream_t);
+template hipError_t launch_stencil_apply<float>(int, int, const float*, const int32_t*, const float*, float*,
+                                                const float*, const float*, int64_t, hipStream_t);
 
 }  // namespace tsmg

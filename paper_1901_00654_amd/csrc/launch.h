@@ -34,6 +34,7 @@ struct TransferArgs {
   int64_t inner;    // product of the sizes of the dimensions after p
   int Jc, Jf;       // coarse / fine length of dimension p
   int subtract;     // prolongation only: out -= value instead of out = value
+  const T* sub;     // restriction only: input is in - sub (null: in)
 };
 
 hipError_t launch_data(int D, bool fp32, int mode, const DataArgs& a, hipStream_t st);
@@ -96,9 +97,10 @@ hipError_t launch_stencil_pass(const double* in, double* out, const double* ctab
                                int64_t inner, hipStream_t st);
 hipError_t launch_stencil_finalize(int D, const double* inter, const double* band, int J, int64_t K, double lam,
                                    double* S64, float* S32, hipStream_t st);
+// epi: 0 out = A x; 1 out = x + w (b - A x); 2 out = A x - b (out must not alias x)
 template <typename T>
-hipError_t launch_stencil_apply(int D, const T* S, const int32_t* offs, const T* c, T* out, int64_t K,
-                                hipStream_t st);
+hipError_t launch_stencil_apply(int D, int epi, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
+                                const T* w, int64_t K, hipStream_t st);
 
 // Radix sort of (key, index) pairs on the low `bits` bits (sort.hip).
 hipError_t sort_pairs(uint32_t* key_in, uint32_t* key_out, uint32_t* val_in, uint32_t* val_out, int64_t n,

@@ -202,7 +202,8 @@ template <typename T>
 void apply_op(Problem* P, int g, const T* c, T* out) {
   Level& L = P->lev[g];
   if (L.stencil) {
-    hip_check(launch_stencil_apply<T>(P->d, lvl_S<T>(L), L.soffs.p, c, out, L.K, P->stream), "stencil apply");
+    hip_check(launch_stencil_apply<T>(P->d, 0, lvl_S<T>(L), L.soffs.p, c, out, nullptr, nullptr, L.K, P->stream),
+              "stencil apply");
     P->applies++;
     return;
   }
@@ -241,9 +242,9 @@ void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract) {
 template void prolong_op<double>(Problem*, int, const double*, double*, bool);
 template void prolong_op<float>(Problem*, int, const float*, float*, bool);
 
-// out (level g-1) = I' r (level g).
+// out (level g-1) = I' (r - sub) (level g); sub may be null.
 template <typename T>
-void restrict_op(Problem* P, int g, const T* r, T* out) {
+void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub) {
   const int D = P->d;
   const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
   T* X = prob_xfer<T>(P);
@@ -261,12 +262,13 @@ void restrict_op(Problem* P, int g, const T* r, T* out) {
     a.inner = inner;
     a.Jc = Jc; a.Jf = Jf;
     a.subtract = 0;
+    a.sub = (p == 0) ? sub : nullptr;
     hip_check(launch_transfer<T>(false, a, P->stream), "restriction pass");
     in = a.out;
   }
 }
-template void restrict_op<double>(Problem*, int, const double*, double*);
-template void restrict_op<float>(Problem*, int, const float*, float*);
+template void restrict_op<double>(Problem*, int, const double*, double*, const double*);
+template void restrict_op<float>(Problem*, int, const float*, float*, const float*);
 
 // x = A_1^-1 b with the precomputed inverse B and one refinement step:
 // x1 = B b, r = b - A_1 x1, x = x1 + B r (all FP64), so the result is as
@@ -291,10 +293,42 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
     return;
   }
   Level& L = P->lev[g];
+  Level& C = P->lev[g - 1];
   const int64_t K = L.K;
   T* t = lvl_t<T>(L);
   const T* w = lvl_w<T>(L);
   const int nu1 = P->opt.nu1, nu2 = P->opt.nu2;
+  if (L.stencil) {
+    // Jacobi sweeps fused into the stencil product, ping-ponging between
+    // alpha and t; the first sweep lands so that the last one ends in alpha.
+    const T* S = lvl_S<T>(L);
+    const int swaps = std::max(0, nu1 - 1) + nu2;
+    T* cur = (swaps % 2 == 0) ? alpha : t;
+    T* oth = (cur == alpha) ? t : alpha;
+    if (nu1 >= 1) {
+      hip_check(launch_jacobi_first<T>(cur, w, b, K, P->stream), "jacobi");
+      for (int j = 1; j < nu1; ++j) {
+        hip_check(launch_stencil_apply<T>(P->d, 1, S, L.soffs.p, cur, oth, b, w, K, P->stream), "jacobi");
+        P->applies++;
+        std::swap(cur, oth);
+      }
+    } else {
+      hip_check(launch_fill<T>(cur, T(0), K, P->stream), "fill");
+    }
+    hip_check(launch_stencil_apply<T>(P->d, 2, S, L.soffs.p, cur, oth, b, w, K, P->stream), "residual");
+    P->applies++;
+    restrict_op<T>(P, g, oth, lvl_b<T>(C), static_cast<const T*>(nullptr));
+    vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
+    prolong_op<T>(P, g, lvl_a<T>(C), cur, true);
+    for (int j = 0; j < nu2; ++j) {
+      hip_check(launch_stencil_apply<T>(P->d, 1, S, L.soffs.p, cur, oth, b, w, K, P->stream), "jacobi");
+      P->applies++;
+      std::swap(cur, oth);
+    }
+    if (cur != alpha)
+      hip_check(launch_scale_copy<T, T>(cur, alpha, K, 1.0, nullptr, P->stream), "copy");
+    return;
+  }
   // pre-smoothing (Alg. 6); the first sweep from zero needs no apply
   if (nu1 >= 1) {
     hip_check(launch_jacobi_first<T>(alpha, w, b, K, P->stream), "jacobi");
@@ -305,11 +339,9 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
   } else {
     hip_check(launch_fill<T>(alpha, T(0), K, P->stream), "fill");
   }
-  // r = A alpha - b, restricted
+  // r = A alpha - b, restricted (the subtraction is fused into the restriction)
   apply_op<T>(P, g, alpha, t);
-  hip_check(launch_residual<T>(t, t, b, K, P->stream), "residual");
-  Level& C = P->lev[g - 1];
-  restrict_op<T>(P, g, t, lvl_b<T>(C));
+  restrict_op<T>(P, g, t, lvl_b<T>(C), b);
   vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
   // alpha -= I e
   prolong_op<T>(P, g, lvl_a<T>(C), alpha, true);
@@ -454,6 +486,7 @@ static void build_stencil(Problem* P, int g) {
   ctab.alloc(ct.size());
   hip_check(hipMemcpyAsync(ctab.p, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, P->stream),
             "upload");
+  hip_check(launch_fill<double>(bufA.p, 0.0, in_sz, P->stream), "fill");
   hip_check(launch_level_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, g, bufA.p, P->stream), "moments");
   double* cur = bufA.p;
   double* nxt = bufB.p;

@@ -122,7 +122,7 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
 
 template <typename T> void apply_op(Problem* P, int g, const T* c, T* out);
 template <typename T> void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract);
-template <typename T> void restrict_op(Problem* P, int g, const T* r, T* out);
+template <typename T> void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub);
 template <typename T> void coarse_op(Problem* P, const T* b, T* x);
 template <typename T> void vcycle_op(Problem* P, int g, const T* b, T* alpha);
 template <typename T> void profile_apply(Problem* P, int g, int reps, double* ms_lambda, double* ms_data);

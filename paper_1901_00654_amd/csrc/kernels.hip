@@ -702,13 +702,16 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, 
   if (threadIdx.x == 0) *slot = v;
 }
 
-// alpha += w p; r -= w v with w = (*num) / (*den) read on the device.
+// alpha += w p; r -= w v with w = (*num) / (*den) read on the device. A step
+// with den <= 0 (a breakdown, which the host reports) leaves both unchanged.
 template <typename TA, typename T>
 __global__ __launch_bounds__(kBlock) void k_cg_step(TA* alpha, T* r, const T* p, const T* v, int64_t K,
                                                     const double* num, const double* den) {
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (k >= K) return;
-  const double w = *num / *den;
+  const double dn = *den;
+  if (!(dn > 0.0) || !isfinite(dn)) return;
+  const double w = *num / dn;
   alpha[k] = TA(double(alpha[k]) + w * double(p[k]));
   r[k] = T(double(r[k]) - w * double(v[k]));
 }
@@ -887,155 +890,30 @@ __global__ __launch_bounds__(kBlock) void k_eval(const double* alpha, const doub
 }
 
 // ---------------------------------------------------------------------------
-// Coarse matrix A_1 (Sec. 3.2.4) from polynomial moments. On a level-1 cell
-// the tensor basis row is v_i = kron_p b(u_ip) with u = t - 1/2, so
-// sum_i v_i v_i' = sum_e M[e] kron_p C_{e_p}, M[e] = sum_i prod_p u_ip^e_p
-// (e in 0..6 per dimension) and C_e[a, a'] the u^e coefficient of b_a b_a'.
-//
-// Moments of the points of level-1 cell blockIdx.y, exponent tuples
-// (e_1..e_{D-1}) = blockIdx.x * kBlock + threadIdx.x with all seven e_0,
-// points of chunk blockIdx.z; accumulated with atomics (mom zeroed before).
+// Coarse matrix A_1 (Sec. 3.2.4): the dense K_1 x K_1 matrix expanded from
+// the level-1 stencil (A1 zeroed first), then inverted by Gauss-Jordan.
 template <int D>
-__global__ __launch_bounds__(kBlock) void k_moments(const double* t64, const uint32_t* cell,
-                                                    const int32_t* off, int64_t n, int G, int chunks,
-                                                    double* mom) {
-  constexpr int E = 7;
-  constexpr int TILE = 64;
-  __shared__ double pw[TILE][D][E];
-  int nrest = 1;
-#pragma unroll
-  for (int p = 1; p < D; ++p) nrest *= E;
-  const int cidx = blockIdx.y;
-  const int S = D * (G - 1);
-  const int64_t c0 = off[size_t(cidx) << S], c1 = off[size_t(cidx + 1) << S];
-  const int64_t len = c1 - c0;
-  const int64_t per = (len + chunks - 1) / chunks;
-  const int64_t b0 = c0 + int64_t(blockIdx.z) * per;
-  const int64_t b1 = min(c1, b0 + per);
-  const int r = blockIdx.x * kBlock + threadIdx.x;
-  int er[D];
-  {
-    int rem = r;
-#pragma unroll
-    for (int p = D - 1; p >= 1; --p) { er[p] = rem % E; rem /= E; }
-    er[0] = 0;
-  }
-  const int sh = G - 1;
-  const uint32_t maskN = (1u << G) - 1u, maskSh = (1u << sh) - 1u;
-  const double scale = 1.0 / double(1u << sh);
-  double acc[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) acc[e] = 0.0;
-  for (int64_t base = b0; base < b1; base += TILE) {
-    __syncthreads();
-    for (int w = threadIdx.x; w < TILE * D; w += kBlock) {
-      const int pt = w / D, p = w % D;
-      const int64_t i = base + pt;
-      double u = 0.0;
-      bool ok = i < b1;
-      if (ok) {
-        const uint32_t cf = cell[i];
-        const uint32_t cfp = (cf >> (G * (D - 1 - p))) & maskN;
-        u = (double(cfp & maskSh) + t64[size_t(p) * n + i]) * scale - 0.5;
-      }
-      double v = ok ? 1.0 : 0.0;
-      for (int e = 0; e < E; ++e) { pw[pt][p][e] = v; v *= u; }
-    }
-    __syncthreads();
-    if (r < nrest) {
-      const int cnt = int(min(int64_t(TILE), b1 - base));
-      for (int pt = 0; pt < cnt; ++pt) {
-        double prod = 1.0;
-#pragma unroll
-        for (int p = 1; p < D; ++p) prod *= pw[pt][p][er[p]];
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] += prod * pw[pt][0][e];
-      }
-    }
-  }
-  if (r < nrest && b0 < b1) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) atomicAdd(&mom[size_t(cidx) * (E * nrest) + size_t(e) * nrest + r], acc[e]);
-  }
-}
-
-// One contraction step: replace exponent e_p by the basis pair (a_p, a'_p).
-// in  [cells][16^p][7][R], out [cells][16^p][16][R], R = 7^(D-1-p).
-__global__ __launch_bounds__(kBlock) void k_contract(const double* in, double* out, const double* ctab,
-                                                     int64_t cellsA, int64_t R, int64_t total) {
-  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (k >= total) return;
-  const int64_t er = k % R;
-  const int64_t rest = k / R;
-  const int pi = int(rest % 16);
-  const int64_t ca = rest / 16;   // (cell, previous pairs) combined index
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < 7; ++e) s += ctab[e * 16 + pi] * in[(ca * 7 + e) * R + er];
-  out[k] = s;
-}
-
-// A_1[k, k'] = sum over level-1 cells c of Gram_c[(k - c), (k' - c)]
-//            + lambda Lambda_1[k, k'].
-template <int D>
-__global__ __launch_bounds__(kBlock) void k_assemble_a1(const double* gram, const double* band, double lam,
-                                                        double* A1) {
-  constexpr int J = 5;
-  int K1 = 1;
-#pragma unroll
-  for (int p = 0; p < D; ++p) K1 *= J;
+__global__ __launch_bounds__(kBlock) void k_dense_from_stencil(const double* S, int J, int64_t K, double* A) {
   const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (t >= int64_t(K1) * K1) return;
-  const int kr = int(t / K1), kc = int(t % K1);
-  int jr[D], jc[D];
-  {
-    int a = kr, b = kc;
+  int NO = 1;
 #pragma unroll
-    for (int p = D - 1; p >= 0; --p) { jr[p] = a % J; a /= J; jc[p] = b % J; b /= J; }
+  for (int p = 0; p < D; ++p) NO *= 7;
+  if (t >= int64_t(NO) * K) return;
+  const int oidx = int(t / K);
+  const int64_t k = t % K;
+  int64_t rk = k, l = 0, stride = 1;
+  int ro = oidx;
+  bool inside = true;
+#pragma unroll
+  for (int p = D - 1; p >= 0; --p) {
+    const int kp = int(rk % J), op = ro % 7 - 3;
+    rk /= J;
+    ro /= 7;
+    inside = inside && kp + op >= 0 && kp + op < J;
+    l += (kp + op) * stride;
+    stride *= J;
   }
-  double s = 0.0;
-  for (int c = 0; c < (1 << D); ++c) {
-    bool ok = true;
-    int64_t pidx = 0;
-#pragma unroll
-    for (int p = 0; p < D; ++p) {
-      const int cp = (c >> (D - 1 - p)) & 1;
-      const int ar = jr[p] - cp, ac = jc[p] - cp;
-      ok = ok && ar >= 0 && ar <= 3 && ac >= 0 && ac <= 3;
-      pidx = pidx * 16 + (ar * 4 + ac);
-    }
-    if (ok) s += gram[size_t(c) * (size_t(1) << (4 * D)) + pidx];
-  }
-  // Lambda_1 entry from the banded 1D factors (|j - l| <= 3 always holds for J = 5).
-  double lm = 0.0;
-  double mv[D], g1v[D], g2v[D];
-#pragma unroll
-  for (int p = 0; p < D; ++p) {
-    const int o = jc[p] - jr[p] + 3;
-    const double* bp = band + p * 3 * J * 7;   // dimension p's factors
-    mv[p] = bp[jr[p] * 7 + o];
-    g1v[p] = bp[J * 7 + jr[p] * 7 + o];
-    g2v[p] = bp[2 * J * 7 + jr[p] * 7 + o];
-  }
-#pragma unroll
-  for (int p = 0; p < D; ++p) {
-    double v = g2v[p];
-#pragma unroll
-    for (int q = 0; q < D; ++q)
-      if (q != p) v *= mv[q];
-    lm += v;
-  }
-#pragma unroll
-  for (int p = 0; p < D; ++p)
-#pragma unroll
-    for (int q = p + 1; q < D; ++q) {
-      double v = 2.0 * g1v[p] * g1v[q];
-#pragma unroll
-      for (int r = 0; r < D; ++r)
-        if (r != p && r != q) v *= mv[r];
-      lm += v;
-    }
-  A1[t] = s + lam * lm;
+  if (inside) A[k * K + l] = S[t];
 }
 
 // In-place Gauss-Jordan inversion without pivoting (A_1 is SPD), step k:
@@ -1566,38 +1444,16 @@ hipError_t launch_eval(int D, const double* alpha, const double* xq, int64_t m, 
   return hipGetLastError();
 }
 
-hipError_t launch_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n, int G,
-                          int chunks, double* mom, hipStream_t st) {
-  int nrest = 1;
-  for (int p = 1; p < D; ++p) nrest *= 7;
-  const dim3 grid(unsigned((nrest + kBlock - 1) / kBlock), 1u << D, unsigned(chunks));
+hipError_t launch_dense_from_stencil(int D, const double* S, int J, int64_t K, double* A, hipStream_t st) {
+  int64_t NO = 1;
+  for (int p = 0; p < D; ++p) NO *= 7;
+  const unsigned g = blocks_for(NO * K);
   switch (D) {
-    case 1: hipLaunchKernelGGL(k_moments<1>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
-    case 2: hipLaunchKernelGGL(k_moments<2>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
-    case 3: hipLaunchKernelGGL(k_moments<3>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
-    case 4: hipLaunchKernelGGL(k_moments<4>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
-    case 5: hipLaunchKernelGGL(k_moments<5>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, chunks, mom); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_contract(const double* in, double* out, const double* ctab, int64_t cellsA, int64_t R,
-                           hipStream_t st) {
-  const int64_t total = cellsA * 16 * R;
-  hipLaunchKernelGGL(k_contract, dim3(blocks_for(total)), dim3(kBlock), 0, st, in, out, ctab, cellsA, R, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_assemble_a1(int D, const double* gram, const double* band, double lam, double* A1, int K1,
-                              hipStream_t st) {
-  const unsigned g = blocks_for(int64_t(K1) * K1);
-  switch (D) {
-    case 1: hipLaunchKernelGGL(k_assemble_a1<1>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
-    case 2: hipLaunchKernelGGL(k_assemble_a1<2>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
-    case 3: hipLaunchKernelGGL(k_assemble_a1<3>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
-    case 4: hipLaunchKernelGGL(k_assemble_a1<4>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
-    case 5: hipLaunchKernelGGL(k_assemble_a1<5>, dim3(g), dim3(kBlock), 0, st, gram, band, lam, A1); break;
+    case 1: hipLaunchKernelGGL(k_dense_from_stencil<1>, dim3(g), dim3(kBlock), 0, st, S, J, K, A); break;
+    case 2: hipLaunchKernelGGL(k_dense_from_stencil<2>, dim3(g), dim3(kBlock), 0, st, S, J, K, A); break;
+    case 3: hipLaunchKernelGGL(k_dense_from_stencil<3>, dim3(g), dim3(kBlock), 0, st, S, J, K, A); break;
+    case 4: hipLaunchKernelGGL(k_dense_from_stencil<4>, dim3(g), dim3(kBlock), 0, st, S, J, K, A); break;
+    case 5: hipLaunchKernelGGL(k_dense_from_stencil<5>, dim3(g), dim3(kBlock), 0, st, S, J, K, A); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

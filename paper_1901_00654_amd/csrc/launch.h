@@ -78,12 +78,7 @@ hipError_t launch_offsets(const uint32_t* key, int64_t n, int64_t ncells, int32_
 hipError_t launch_eval(int D, const double* alpha, const double* xq, int64_t m, const BoxArgs& box, double* yq,
                        hipStream_t st);
 
-hipError_t launch_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n, int G,
-                          int chunks, double* mom, hipStream_t st);
-hipError_t launch_contract(const double* in, double* out, const double* ctab, int64_t cellsA, int64_t R,
-                           hipStream_t st);
-hipError_t launch_assemble_a1(int D, const double* gram, const double* band, double lam, double* A1, int K1,
-                              hipStream_t st);
+hipError_t launch_dense_from_stencil(int D, const double* S, int J, int64_t K, double* A, hipStream_t st);
 hipError_t launch_gj_step(double* A, int K, int k, double* row, double* col, double* piv, hipStream_t st);
 hipError_t launch_symmetrize(double* A, int K, hipStream_t st);
 // out = base + s * A v (dense K x K, FP64 arithmetic); base may be null.

@@ -535,51 +535,24 @@ static bool want_stencil(const Problem* P, const Level& L, size_t free_bytes) {
   return entries * 1.6e-12 < double(P->n) * P4 * 0.5e-12;
 }
 
-// A_1 = sum over level-1 cells of the cell Gram (from moments) + lambda
-// Lambda_1, then its inverse by Gauss-Jordan; pivots checked for positivity.
+// A_1 expanded from the level-1 stencil (built here if the apply path did
+// not build it), then inverted by Gauss-Jordan; pivots checked for
+// positivity.
 static void build_coarse(Problem* P) {
   const int D = P->d;
-  const int cells = 1 << D;
-  int64_t e7 = 1;
-  for (int p = 0; p < D; ++p) e7 *= 7;
-  const int64_t K1 = P->lev[1].K;
+  Level& L1 = P->lev[1];
+  const int64_t K1 = L1.K;
   P->K1 = int(K1);
-  DevBuf<double> mom, bufA, bufB, ctab, row, col, piv;
-  mom.alloc(size_t(cells) * e7);
-  hip_check(launch_fill<double>(mom.p, 0.0, int64_t(cells) * e7, P->stream), "fill");
-  int chunks = int(std::min<int64_t>(64, std::max<int64_t>(1, P->n / (int64_t(cells) * 32768))));
-  hip_check(launch_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, chunks, mom.p, P->stream), "moments");
-  std::vector<double> ct;
-  pair_table(ct);
-  ctab.alloc(ct.size());
-  hip_check(hipMemcpyAsync(ctab.p, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, P->stream),
-            "upload");
-  // contraction buffers: step p output = cells * 16^(p+1) * 7^(D-1-p)
-  int64_t maxsz = 0;
-  {
-    int64_t a16 = 1, r7 = e7;
-    for (int p = 0; p < D; ++p) {
-      r7 /= 7;
-      a16 *= 16;
-      maxsz = std::max(maxsz, int64_t(cells) * a16 * r7);
-    }
+  if (!L1.S64.p) {
+    build_stencil(P, 1);
+    L1.stencil = (P->opt.stencil_mode != 1);
   }
-  bufA.alloc(size_t(maxsz));
-  bufB.alloc(size_t(maxsz));
-  const double* in = mom.p;
-  int64_t a16 = 1, r7 = e7;
-  double* outp = nullptr;
-  for (int p = 0; p < D; ++p) {
-    r7 /= 7;
-    outp = (p % 2 == 0) ? bufA.p : bufB.p;
-    hip_check(launch_contract(in, outp, ctab.p, int64_t(cells) * a16, r7, P->stream), "contract");
-    a16 *= 16;
-    in = outp;
-  }
+  DevBuf<double> row, col, piv;
   P->A1.alloc(size_t(K1) * K1);
   P->A1inv.alloc(size_t(K1) * K1);
   P->cwork.alloc(size_t(2 * K1));
-  hip_check(launch_assemble_a1(D, outp, P->lev[1].band64.p, P->lam, P->A1.p, int(K1), P->stream), "assemble");
+  hip_check(launch_fill<double>(P->A1.p, 0.0, K1 * K1, P->stream), "fill");
+  hip_check(launch_dense_from_stencil(D, L1.S64.p, L1.J, K1, P->A1.p, P->stream), "assemble");
   hip_check(hipMemcpyAsync(P->A1inv.p, P->A1.p, sizeof(double) * K1 * K1, hipMemcpyDeviceToDevice, P->stream),
             "copy A1");
   // diagonal before inversion, for the pivot test

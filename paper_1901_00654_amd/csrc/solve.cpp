@@ -157,7 +157,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
     vcycle_op<float>(P, G, rin, z);
     hip_check(launch_scale_copy<float, float>(z, p, K, 1.0, nullptr, st), "copy");
     dot_op<float, float>(P, rin, z, K, sa);
-    for (;;) {
+    for (int inner = 0;; ++inner) {
       apply_op<float>(P, G, p, w);
       dot_op<float, float>(P, p, w, K, kPV);
       hip_check(launch_cg_step<float, float>(dl, rin, p, w, K, P->slot(sa), P->slot(kPV), st), "cg step");
@@ -165,8 +165,16 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
       double h[2];
       P->read_slots(kPV, 2, h);
       ++inner_total;
-      if (!finite_pos(h[0]) || !std::isfinite(h[1]))
-        throw Error{TS_EBREAKDOWN, "inner CG breakdown: p'Ap = " + std::to_string(h[0])};
+      if (!std::isfinite(h[0])) throw Error{TS_EBREAKDOWN, "inner CG breakdown: p'Ap is not finite"};
+      if (!(h[0] > 0.0)) {
+        // FP32 rounding made A look indefinite (kappa(A) beyond single
+        // precision). The step was skipped on the device; keep the iterate,
+        // or on the first step take the V-cycle correction z = p itself, and
+        // let the FP64 refinement carry on.
+        if (inner == 0) hip_check(launch_scale_copy<float, float>(p, dl, K, 1.0, nullptr, st), "copy");
+        break;
+      }
+      if (!std::isfinite(h[1])) throw Error{TS_EBREAKDOWN, "inner CG breakdown: residual is not finite"};
       if (std::sqrt(h[1]) <= P->opt.inner_tol || inner_total >= P->opt.max_iter) break;
       vcycle_op<float>(P, G, rin, z);
       dot_op<float, float>(P, rin, z, K, sb);

@@ -132,6 +132,18 @@ def apply_rate(tsmg, torch, w, stream, reps):
     return out
 
 
+def copy_calibration(torch):
+    """A plain streaming kernel of known size (1 GiB read, 1 GiB written, as
+    an elementwise multiply by one, which runs as a kernel where a same-type
+    copy may go to a DMA engine), for scaling HBM byte counters."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    return src.numel() * 8
+
+
 def cpu_baseline(w, applies_per_solve, budget_s=20.0):
     """The oracle's matrix-free FP64 apply (NumPy) on the same points, timed
     for about budget_s seconds, scaled to solves/s with the number of operator
@@ -190,12 +202,7 @@ def main():
         wk = workloads.CONFIGS[args.only_apply]()
         res = apply_rate(tsmg, torch, wk, stream, args.reps)
         if args.copy_calibration:
-            src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-            dst = torch.empty_like(src)
-            for _ in range(3):
-                dst.copy_(src)
-            torch.cuda.synchronize()
-            res["copy_calibration_bytes"] = src.numel() * 8
+            res["copy_calibration_bytes"] = copy_calibration(torch)
         print(json.dumps(res), flush=True)
         return
     w = workloads.c2()
@@ -261,12 +268,7 @@ def main():
         result["apply_sweep"] = sweep
 
     if args.copy_calibration:
-        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        result["copy_calibration_bytes"] = src.numel() * 8
+        result["copy_calibration_bytes"] = copy_calibration(torch)
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(w, info["applies"])

@@ -16,8 +16,9 @@ What is here, each module citing the passage it follows:
                formula (eq. 2.5, 2.6), the grid hierarchy (Sec. 3.2.1).
 - ``mg``       the assembled-matrix V-cycle (Alg. 7 with the Jacobi
                smoother of Alg. 6), MGCG (Alg. 8), plain CG, the damping
-               parameter by a Gershgorin-type bound (a reading: the paper
-               gives no value), the direct solve.
+               parameter from a short Lanczos estimate of the largest
+               eigenvalue of D^-1 A (a reading: the paper gives no value),
+               the direct solve.
 - ``matfree``  a matrix-free CPU apply and per-coefficient sampled outputs
                for sizes where assembly is too large.
 

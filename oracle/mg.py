@@ -7,7 +7,7 @@ prolongation (Sec. 3.2.3), recursion with a zero start, correction
 alpha <- alpha - I e, post-smoothing; the coarsest level g = 1 is solved
 exactly with a dense Cholesky factor (Sec. 3.2.4). MGCG follows Alg. 8.
 
-Readings where the paper is silent or inconsistent (listed in the design doc):
+Readings where the paper is silent or inconsistent:
 - Alg. 8 takes the step length as ||r||^2 / p'v but the direction update
   with r'z; the preconditioned step r'z / p'v is used (standard PCG).
 - The start is alpha = 0 and the stop is ||r_k||_2 / ||b||_2 <= tol on the

@@ -61,10 +61,12 @@ typedef enum {
 
 typedef enum {
     TS_FP64 = 0,          /* every operation in FP64                                 */
-    TS_MIXED_FP32 = 1,    /* FP64 residuals in an iterative-refinement loop around a
-                             PCG whose applies and V-cycle run in FP32; FP64 only for
-                             inner products, the refinement residual and the coarse
-                             solve                                                   */
+    TS_MIXED_FP32 = 1,    /* PCG whose recurrences, operator applies and V-cycle run
+                             in FP32, with FP64 inner products, an FP64 coarse solve
+                             and reliable updates: the FP32 correction is added to the
+                             FP64 solution and the FP32 residual replaced by the FP64
+                             true residual each time it has dropped by inner_tol
+                             (iterative refinement that keeps the search direction) */
     TS_MIXED_BF16 = 2     /* reserved: bfloat16 storage of the per-point 1D basis values
                              of the inner operator; not available in this version
                              (TS_EINVAL)                                              */
@@ -81,8 +83,9 @@ typedef struct {
     int max_iter;          /* outer CG iterations (FP64) or total inner iterations
                               (mixed); default 10000                                 */
     double tol;            /* stop when ||b - A alpha||_2 / ||b||_2 <= tol; 1e-8       */
-    double inner_tol;      /* mixed: relative reduction per refinement step; 1e-4     */
-    int max_refine;        /* mixed: refinement steps; default 50                    */
+    double inner_tol;      /* mixed: the FP32 residual reduction, since the last FP64
+                              update, that triggers the next one; in (0, 1), 0.1      */
+    int max_refine;        /* mixed: most FP64 residual updates; default 50          */
     int points_per_block;  /* data-term work per workgroup; 0 = automatic            */
     int stencil_mode;      /* levels whose A_g is assembled at setup as a 7^d-point
                               stencil (same operator, applied as a stencil product):
@@ -93,8 +96,9 @@ typedef struct {
 } ts_options;
 
 typedef struct {
-    int iterations;        /* CG iterations (FP64) or inner PCG iterations (mixed)   */
-    int refinements;       /* mixed: outer refinement steps; FP64: 0                 */
+    int iterations;        /* CG iterations (FP64 or, mixed, FP32 ones)              */
+    int refinements;       /* mixed: FP64 residual updates; FP64: restarts of CG from
+                              the true residual                                       */
     int converged;         /* 1 if rel_residual <= tol                                */
     double rel_residual;   /* ||b - A alpha||_2 / ||b||_2 recomputed in FP64 at exit  */
     double setup_s;        /* wall time of ts_create                                 */
@@ -218,6 +222,108 @@ ts_status ts_profile_apply(ts_problem* p, int level, int fp32, int reps, double*
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* ts_last_error(void);
+
+/* Device memory of a problem as allocated by the library: *resident bytes held
+ * after setup, *peak the most held at once during setup (sort and stencil
+ * temporaries included). Either pointer may be NULL. */
+ts_status ts_memory(const ts_problem* p, size_t* resident, size_t* peak);
+
+/* Upper estimate of the peak device bytes a problem of this shape needs from
+ * ts_create through ts_solve (the caller's x and y excluded), under the same
+ * stencil policy as ts_create. intervals: host, d ints (as for ts_create).
+ * opt may be NULL. */
+ts_status ts_footprint(int d, int q, const int32_t* intervals, int64_t n, const ts_options* opt,
+                       size_t* bytes);
+
+/*
+ * Serving loop: independent smoothing requests (any d, grid, point count, lambda,
+ * precision) submitted as they arrive and solved concurrently on one GPU.
+ *
+ * A server runs `slots` worker threads, each with its own HIP stream. A worker
+ * takes the oldest queued request as soon as it is free and the request's
+ * estimated peak device memory (ts_footprint plus its points) fits in what the
+ * memory budget has left; the request's points, hierarchy and solver state then
+ * live on the device until its solve ends, and the kernels of different
+ * requests overlap on the GPU. Admission is first in, first out: a request
+ * that does not fit yet holds back the ones behind it. Each request is solved
+ * exactly as ts_create + ts_solve would solve it alone (zero start vector);
+ * only the order of floating-point atomic additions differs.
+ *
+ * Handles are thread-safe: any thread may submit, poll or wait.
+ */
+typedef struct ts_server ts_server;
+
+typedef struct {
+    size_t memory_budget;  /* bytes of device memory admitted requests may hold at once;
+                              0 = half of the free device memory at ts_server_create   */
+    int slots;             /* requests solved at once (worker threads); default 4, 1..64 */
+} ts_server_options;
+
+typedef struct {
+    int d, q;              /* as for ts_create                                        */
+    const int32_t* intervals;  /* host, d ints                                        */
+    const double* lo;      /* host, d doubles                                         */
+    const double* hi;      /* host, d doubles                                         */
+    int64_t n;
+    const double* x;       /* HOST, n*d doubles row-major; copied by ts_server_submit  */
+    const double* y;       /* HOST, n doubles; copied                                  */
+    double lambda;
+    const ts_options* opt; /* solver options (NULL = defaults); opt->stream is ignored */
+} ts_request;
+
+typedef struct {
+    ts_status status;      /* outcome of the request's setup and solve                */
+    ts_solve_info info;
+    int64_t K;             /* number of coefficients of the solution                   */
+    size_t footprint;      /* device bytes reserved for it at admission                */
+    size_t peak_bytes;     /* device bytes its problem held at most (setup measured)   */
+    double t_submit;       /* seconds since ts_server_create: submitted               */
+    double t_start;        /* admitted to a worker                                    */
+    double t_done;         /* solution copied to host memory                          */
+    char error[256];       /* message when status < 0                                 */
+} ts_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, queued;
+    int active;            /* requests on the device now                              */
+    int max_active;        /* most requests on the device at once so far              */
+    size_t in_use;         /* footprint bytes reserved now                            */
+    size_t max_in_use;     /* most footprint bytes reserved at once so far            */
+    size_t memory_budget;
+} ts_server_stats;
+
+/* Fills *opt with the defaults (memory_budget 0, slots 4). */
+void ts_server_default_options(ts_server_options* opt);
+
+/* Starts a server on the current device. Returns TS_EINVAL for slots outside
+ * 1..64, TS_EDEVICE if no device is usable. */
+ts_status ts_server_create(const ts_server_options* opt, ts_server** out);
+
+/* Queues one request and returns at once with its ticket. The host arrays of
+ * the request are copied; the caller may reuse them on return. Arguments are
+ * checked as far as possible without the device (TS_EINVAL); a request whose
+ * footprint exceeds the whole budget is refused with TS_ENOMEM. Errors found
+ * later (e.g. points outside the box, a singular A_1) are reported in its
+ * ts_result. */
+ts_status ts_server_submit(ts_server* s, const ts_request* req, uint64_t* ticket);
+
+/* *done = 1 if the request has finished (successfully or not), else 0. */
+ts_status ts_server_poll(ts_server* s, uint64_t ticket, int* done);
+
+/* Blocks until the request has finished, copies its solution (K doubles, C
+ * order, finest level) into the HOST buffer alpha when alpha is not NULL and
+ * capacity >= K, fills *result (may be NULL) and releases the ticket. Returns
+ * TS_EINVAL for an unknown or already released ticket or a too small buffer;
+ * the request's own outcome is result->status. */
+ts_status ts_server_wait(ts_server* s, uint64_t ticket, double* alpha, int64_t capacity,
+                         ts_result* result);
+
+/* Counters of the server (see ts_server_stats). */
+ts_status ts_server_get_stats(ts_server* s, ts_server_stats* stats);
+
+/* Finishes every queued and running request, stops the workers and frees the
+ * server (results not yet waited for are discarded). NULL is a no-op. */
+void ts_server_destroy(ts_server* s);
 
 #ifdef __cplusplus
 }

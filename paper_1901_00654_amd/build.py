@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtsmg.so")
-SOURCES = ["kernels.hip", "sort.hip", "problem.cpp", "solve.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "sort.hip", "problem.cpp", "solve.cpp", "api.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 COMMON = [
@@ -56,7 +56,7 @@ def build(jobs=None, verbose=False):
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(r[0] for r in failed))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + [r[1] for r in results]
+    cmd = [_hipcc(), "-shared", "-fPIC", "-pthread", "--offload-arch=" + ARCH, "-o", tmp] + [r[1] for r in results]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stderr)

@@ -7,6 +7,7 @@
 #include <exception>
 #include <string>
 
+#include "api_util.h"
 #include "problem.h"
 
 namespace tsmg {
@@ -16,22 +17,6 @@ void rhs_op(Problem* P, double* b);
 
 using tsmg::Error;
 using tsmg::Problem;
-
-#define TS_API_BEGIN try {
-#define TS_API_END                                   \
-  }                                                  \
-  catch (const Error& e) {                           \
-    tsmg::set_error(e.msg);                          \
-    return e.code;                                   \
-  }                                                  \
-  catch (const std::exception& e) {                  \
-    tsmg::set_error(e.what());                       \
-    return TS_EDEVICE;                               \
-  }                                                  \
-  catch (...) {                                      \
-    tsmg::set_error("unknown internal error");       \
-    return TS_EDEVICE;                               \
-  }
 
 namespace {
 
@@ -66,7 +51,7 @@ void ts_default_options(ts_options* o) {
   o->precision = TS_FP64;
   o->max_iter = 10000;
   o->tol = 1e-8;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 0.1;
   o->max_refine = 50;
   o->points_per_block = 0;
   o->stencil_mode = 0;
@@ -269,6 +254,33 @@ ts_status ts_profile_apply(ts_problem* p, int level, int fp32, int reps, double*
   need(ms_lambda && ms_data, "outputs must not be null");
   if (fp32) tsmg::profile_apply<float>(P, level, reps, ms_lambda, ms_data);
   else tsmg::profile_apply<double>(P, level, reps, ms_lambda, ms_data);
+  return TS_OK;
+  TS_API_END
+}
+
+ts_status ts_memory(const ts_problem* p, size_t* resident, size_t* peak) {
+  TS_API_BEGIN
+  Problem* P = get(p);
+  if (resident) *resident = size_t(P->mem_resident);
+  if (peak) *peak = size_t(P->mem_peak);
+  return TS_OK;
+  TS_API_END
+}
+
+ts_status ts_footprint(int d, int q, const int32_t* intervals, int64_t n, const ts_options* opt,
+                       size_t* bytes) {
+  TS_API_BEGIN
+  need(bytes != nullptr, "bytes must not be null");
+  need(q == 3, "only cubic splines (q = 3) are supported");
+  need(d >= 1 && d <= tsmg::kMaxDim, "d must be in 1..5");
+  need(intervals != nullptr && n >= 1, "intervals must not be null and n >= 1");
+  const int N = intervals[0];
+  for (int p = 0; p < d; ++p) need(intervals[p] == N, "all dimensions must have the same number of intervals");
+  need(N >= 2 && (N & (N - 1)) == 0, "intervals must be a power of two >= 2");
+  ts_options o;
+  ts_default_options(&o);
+  if (opt) o = *opt;
+  *bytes = size_t(tsmg::footprint_bytes(d, N, n, o, 0.0));
   return TS_OK;
   TS_API_END
 }

@@ -310,6 +310,13 @@ __device__ __forceinline__ void point_scatter(const PointVals<D, T>& q, T s, T (
   }
 }
 
+// Byte offset of the FP64 patch accumulator in the dynamic LDS of the point
+// pass: after the staged coefficient patch (apply with staging), else 0.
+template <typename T, int MODE, bool STAGE_C>
+__host__ __device__ constexpr size_t lacc_offset(int patch) {
+  return (MODE == kApply && STAGE_C) ? ((size_t(patch) * sizeof(T) + 15) & ~size_t(15)) : 0;
+}
+
 template <int D, typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   using GP = Group<D>;
@@ -333,7 +340,9 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   int patch = 1;
 #pragma unroll
   for (int p = 0; p < D; ++p) patch *= P;
-  T* lacc = (MODE == kApply && STAGE_C) ? lc + patch : lc;
+  // the patch accumulator is FP64 for both precisions: LDS float atomics are
+  // several times slower than FP64 ones on gfx950
+  double* lacc = reinterpret_cast<double*>(smem_raw + lacc_offset<T, MODE, STAGE_C>(patch));
 
   int st[D];
   st[D - 1] = 1;
@@ -410,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
         }
         lc[e] = cin[gidx];
       }
-      lacc[e] = T(0);
+      lacc[e] = 0.0;
     }
     int n_items_all;
     const int first = block_exclusive_scan(nch, scan_sh, &n_items_all);
@@ -489,13 +498,13 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const int off = (D == 1) ? v : ((v >> 2) * sa + (v & 3));
-        atomicAdd(&lacc[base + off], acc[v]);
+        atomicAdd(&lacc[base + off], double(acc[v]));
       }
     }
     __syncthreads();
 
     for (int e = threadIdx.x; e < patch; e += kBlock) {
-      const T v = lacc[e];
+      const T v = T(lacc[e]);
       if (v != T(0)) {
         int rem = e;
         int64_t gidx = 0;
@@ -1211,7 +1220,7 @@ static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
   const int Tg = 1 << a.tb;
   int patch = 1;
   for (int p = 0; p < D; ++p) patch *= (Tg + kDeg);
-  const size_t lds = size_t(patch) * sizeof(T) * ((MODE == kApply && Group<D>::STAGE_C) ? 2 : 1);
+  const size_t lds = lacc_offset<T, MODE, Group<D>::STAGE_C>(patch) + size_t(patch) * sizeof(double);
   if (a.ppb > Group<D>::PPB) return hipErrorInvalidValue;
   const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
   if (grid == 0) return hipSuccess;

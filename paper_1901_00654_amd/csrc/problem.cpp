@@ -16,6 +16,7 @@
 namespace tsmg {
 
 thread_local std::string g_last_error;
+thread_local MemCount g_mem;
 
 void set_error(const std::string& m) { g_last_error = m; }
 
@@ -521,18 +522,54 @@ static void build_stencil(Problem* P, int g) {
 // in automatic mode, its estimated time (a stream of 8 bytes per entry at
 // about 5 TB/s) must beat the point pass (about 0.5 ps per point and patch
 // entry, as measured for the FP64 point pass on MI355X).
-static bool want_stencil(const Problem* P, const Level& L, size_t free_bytes) {
-  if (P->opt.stencil_mode == 1) return false;
-  double NO = 1.0, P4 = 1.0;
-  for (int p = 0; p < P->d; ++p) { NO *= 7.0; P4 *= 4.0; }
-  const double entries = NO * double(L.K);
-  double transient = 1.0;
-  for (int p = 0; p < P->d; ++p) transient *= 7.0 * L.J;
+static bool want_stencil(int d, int J, int64_t n, int mode, double budget) {
+  if (mode == 1) return false;
+  double NO = 1.0, P4 = 1.0, K = 1.0, transient = 1.0;
+  for (int p = 0; p < d; ++p) { NO *= 7.0; P4 *= 4.0; K *= J; transient *= 7.0 * J; }
+  const double entries = NO * K;
   const double bytes = entries * 12.0 + 2.0 * transient * 8.0;
-  const double budget = std::min(16e9, 0.4 * double(free_bytes));
   if (bytes > budget) return false;
-  if (P->opt.stencil_mode == 2) return true;
-  return entries * 1.6e-12 < double(P->n) * P4 * 0.5e-12;
+  if (mode == 2) return true;
+  return entries * 1.6e-12 < double(n) * P4 * 0.5e-12;
+}
+
+static double stencil_budget_for(double stencil_budget) {
+  if (stencil_budget > 0.0) return stencil_budget;
+  size_t free_b = 0, total_b = 0;
+  hip_check(hipMemGetInfo(&free_b, &total_b), "meminfo");
+  return std::min(16e9, 0.4 * double(free_b));
+}
+
+int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double stencil_budget) {
+  int G = 0;
+  while ((1 << G) < N) ++G;
+  auto ipow = [](int64_t b, int e) { int64_t r = 1; for (int i = 0; i < e; ++i) r *= b; return r; };
+  const int64_t KG = ipow(N + kDeg, d);
+  const int64_t cells = int64_t(1) << (G * d);
+  // points: t64, t32, C-order cell, Morton key, responses; cell offsets
+  const int64_t points = n * (12 * int64_t(d) + 16) + 4 * (cells + 1);
+  // binning and sort temporaries (keys and indices double-buffered, radix
+  // sort scratch bounded by another key/value pair and 1 MB)
+  const int64_t sort_tmp = 24 * n + (1 << 20);
+  int64_t levels = 0, stencils = 0, stencil_tmp = 0;
+  for (int g = 1; g <= G; ++g) {
+    const int J = (1 << g) + kDeg;
+    const int64_t K = ipow(J, d);
+    levels += 56 * K + int64_t(d) * 3 * J * 7 * 12;
+    // level 1 always carries its stencil: A_1 is expanded from it
+    if (g == 1 || want_stencil(d, J, n, opt.stencil_mode, stencil_budget_for(stencil_budget))) {
+      stencils += ipow(7, d) * K * 12 + ipow(7, d) * 4;
+      stencil_tmp = std::max(stencil_tmp, 2 * ipow(7 * int64_t(J), d) * 8 + (1 << 16));
+    }
+  }
+  const int64_t K1 = ipow(2 + kDeg, d);
+  const int64_t coarse = 2 * K1 * K1 * 8 + 2 * K1 * 8;
+  const int64_t finest = KG * (6 * 12 + 2 * 12 + 5 * 8 + 5 * 4);
+  const int64_t misc = 16 * 8 + kMaxPartials * 8 + 64;
+  const int64_t steady = points + levels + stencils + coarse + finest + misc;
+  // allocation granularity: round every buffer up, roughly 40 buffers per level
+  const int64_t slack = int64_t(64) * 4096 * (G + 2);
+  return steady + std::max(sort_tmp, stencil_tmp) + slack;
 }
 
 // A_1 expanded from the level-1 stencil (built here if the apply path did
@@ -581,8 +618,11 @@ static void build_coarse(Problem* P) {
 }
 
 Problem* create_problem(int d, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
-                        const double* x, const double* y, double lam, const ts_options* opt) {
+                        const double* x, const double* y, double lam, const ts_options* opt,
+                        double stencil_budget) {
   auto t0 = std::chrono::steady_clock::now();
+  const int64_t mem_base = g_mem.live;
+  g_mem.peak = g_mem.live;
   if (d < 1 || d > kMaxDim) throw Error{TS_EINVAL, "d must be in 1..5"};
   if (!intervals || !lo || !hi || !x || !y) throw Error{TS_EINVAL, "null argument"};
   if (n < 1) throw Error{TS_EINVAL, "n must be >= 1"};
@@ -731,10 +771,9 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
 
     // --- assembled stencils for the levels where they pay (same A_g)
     {
-      size_t free_b = 0, total_b = 0;
-      hip_check(hipMemGetInfo(&free_b, &total_b), "meminfo");
+      const double budget = stencil_budget_for(stencil_budget);
       for (int g = 1; g <= G; ++g)
-        if (want_stencil(P, P->lev[g], free_b)) build_stencil(P, g);
+        if (want_stencil(d, P->lev[g].J, n, P->opt.stencil_mode, budget)) build_stencil(P, g);
     }
 
     // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)
@@ -755,6 +794,8 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     hip_check(hipStreamSynchronize(st), "sync");
     P->applies = 0;
     P->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    P->mem_resident = g_mem.live - mem_base;
+    P->mem_peak = g_mem.peak - mem_base;
     return P;
   } catch (...) {
     delete P;

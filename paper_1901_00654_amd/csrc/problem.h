@@ -18,6 +18,15 @@ struct Error {
 void hip_check(hipError_t e, const char* what);
 void set_error(const std::string& m);
 
+// Device bytes held by DevBuf objects allocated on this thread (live) and
+// the high-water mark since the last reset; a problem records both around
+// its setup.
+struct MemCount {
+  int64_t live = 0;
+  int64_t peak = 0;
+};
+extern thread_local MemCount g_mem;
+
 // Owning device buffer (freed on destruction). Allocation failure throws
 // Error{TS_ENOMEM}.
 template <typename T>
@@ -43,9 +52,14 @@ struct DevBuf {
       throw Error{TS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
     }
     n = count;
+    g_mem.live += int64_t(count * sizeof(T));
+    if (g_mem.live > g_mem.peak) g_mem.peak = g_mem.live;
   }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      (void)hipFree(p);
+      g_mem.live -= int64_t(n * sizeof(T));
+    }
     p = nullptr;
     n = 0;
   }
@@ -111,14 +125,23 @@ struct Problem {
 
   double setup_s = 0.0;
   int64_t applies = 0;
+  int64_t mem_resident = 0;   // device bytes held after setup
+  int64_t mem_peak = 0;       // most device bytes held during setup
 
   double* slot(int i);
   void read_slots(int first, int count, double* host);
   ~Problem();
 };
 
+// stencil_budget > 0 caps the bytes of assembled stencils per level at that
+// value; 0 takes min(16 GB, 40% of the free device memory).
 Problem* create_problem(int d, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
-                        const double* x, const double* y, double lam, const ts_options* opt);
+                        const double* x, const double* y, double lam, const ts_options* opt,
+                        double stencil_budget = 0.0);
+
+// Upper estimate of the device bytes create_problem and a solve hold at
+// their peak, for the same arguments (the points themselves excluded).
+int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double stencil_budget);
 
 template <typename T> void apply_op(Problem* P, int g, const T* c, T* out);
 template <typename T> void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract);

@@ -112,8 +112,16 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
   return info->converged ? TS_OK : TS_ENOTCONV;
 }
 
-// Iterative refinement: FP64 residual, FP32 MGCG correction on the
-// normalised residual, FP64 update.
+// Mixed precision: the CG recurrences, the operator applies and the V-cycle
+// run in FP32 on the residual scaled by 1/||b||, with FP64 dot products. The
+// FP32 correction is accumulated separately; whenever the FP32 residual has
+// dropped by the factor inner_tol since the last update (or CG would stop),
+// the correction is added to alpha in FP64, the true residual b - A alpha is
+// recomputed with the FP64 operator and replaces the FP32 one, and the search
+// direction is kept (CG with reliable updates: iterative refinement that does
+// not restart the Krylov space). A non-positive p'Ap in FP32 (kappa(A) beyond
+// single precision) forces an update that takes the V-cycle correction and
+// restarts the direction.
 static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_info* info) {
   const int G = P->G;
   const int64_t K = P->lev[G].K;
@@ -132,61 +140,72 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
     return TS_OK;
   }
   const double bnorm = std::sqrt(bb);
-  if (!use_start) hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
   const double tol = P->opt.tol;
-  int inner_total = 0, refine = 0;
-  double rel = 1.0;
-  bool first = true;
-  for (;;) {
-    if (first && !use_start) {
-      hip_check(launch_scale_copy<double, double>(b, r, K, 1.0, nullptr, st), "copy");
-    } else {
-      true_residual(P, alpha, b, r, v);
-    }
-    first = false;
-    dot_op<double, double>(P, r, r, K, kRR64);
-    double rr;
-    P->read_slots(kRR64, 1, &rr);
-    if (!std::isfinite(rr)) throw Error{TS_EBREAKDOWN, "residual is not finite"};
-    rel = std::sqrt(rr) / bnorm;
-    if (rel <= tol || inner_total >= P->opt.max_iter || refine >= P->opt.max_refine) break;
-    // inner FP32 MGCG on r / ||r||
-    hip_check(launch_scale_copy<double, float>(r, rin, K, 1.0, P->slot(kRR64), st), "to fp32");
+  const double delta = (P->opt.inner_tol > 0.0 && P->opt.inner_tol < 1.0) ? P->opt.inner_tol : 0.1;
+  if (use_start) {
+    true_residual(P, alpha, b, r, v);
+  } else {
+    hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
+    hip_check(launch_scale_copy<double, double>(b, r, K, 1.0, nullptr, st), "copy");
+  }
+  dot_op<double, double>(P, r, r, K, kRR64);
+  double rr;
+  P->read_slots(kRR64, 1, &rr);
+  double rel = std::sqrt(rr) / bnorm;
+  int total = 0, updates = 0;
+  if (!(rel <= tol)) {
+    if (!std::isfinite(rel)) throw Error{TS_EBREAKDOWN, "residual is not finite"};
+    hip_check(launch_scale_copy<double, float>(r, rin, K, 1.0 / bnorm, nullptr, st), "to fp32");
     hip_check(launch_fill<float>(dl, 0.0f, K, st), "fill");
+    double rmax = rel;        // FP32 residual norm (relative to ||b||) at the last update
+    bool fresh = true;        // dl is zero and p = z (first step since a (re)start)
     int sa = kRZa, sb = kRZb;
     vcycle_op<float>(P, G, rin, z);
     hip_check(launch_scale_copy<float, float>(z, p, K, 1.0, nullptr, st), "copy");
     dot_op<float, float>(P, rin, z, K, sa);
-    for (int inner = 0;; ++inner) {
+    for (;;) {
       apply_op<float>(P, G, p, w);
       dot_op<float, float>(P, p, w, K, kPV);
       hip_check(launch_cg_step<float, float>(dl, rin, p, w, K, P->slot(sa), P->slot(kPV), st), "cg step");
       dot_op<float, float>(P, rin, rin, K, kRR);
       double h[2];
       P->read_slots(kPV, 2, h);
-      ++inner_total;
-      if (!std::isfinite(h[0])) throw Error{TS_EBREAKDOWN, "inner CG breakdown: p'Ap is not finite"};
-      if (!(h[0] > 0.0)) {
-        // FP32 rounding made A look indefinite (kappa(A) beyond single
-        // precision). The step was skipped on the device; keep the iterate,
-        // or on the first step take the V-cycle correction z = p itself, and
-        // let the FP64 refinement carry on.
-        if (inner == 0) hip_check(launch_scale_copy<float, float>(p, dl, K, 1.0, nullptr, st), "copy");
-        break;
+      ++total;
+      if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
+        throw Error{TS_EBREAKDOWN, "mixed CG breakdown: non-finite scalar"};
+      const bool breakdown = !(h[0] > 0.0);   // the device skipped the step
+      if (breakdown && fresh) hip_check(launch_scale_copy<float, float>(p, dl, K, 1.0, nullptr, st), "copy");
+      const double rn = std::sqrt(h[1]);
+      if (breakdown || rn <= tol || rn <= delta * rmax || total >= P->opt.max_iter) {
+        // reliable update: alpha += ||b|| dl in FP64, FP64 true residual
+        hip_check(launch_axpy_conv<float, double>(dl, alpha, K, bnorm, nullptr, st), "update");
+        hip_check(launch_fill<float>(dl, 0.0f, K, st), "fill");
+        true_residual(P, alpha, b, r, v);
+        dot_op<double, double>(P, r, r, K, kRR64);
+        P->read_slots(kRR64, 1, &rr);
+        ++updates;
+        rel = std::sqrt(rr) / bnorm;
+        if (!std::isfinite(rel)) throw Error{TS_EBREAKDOWN, "residual is not finite"};
+        if (rel <= tol || total >= P->opt.max_iter || updates >= P->opt.max_refine) break;
+        hip_check(launch_scale_copy<double, float>(r, rin, K, 1.0 / bnorm, nullptr, st), "to fp32");
+        rmax = rel;
+        if (breakdown) {   // restart the direction from the new residual
+          vcycle_op<float>(P, G, rin, z);
+          hip_check(launch_scale_copy<float, float>(z, p, K, 1.0, nullptr, st), "copy");
+          dot_op<float, float>(P, rin, z, K, sa);
+          fresh = true;
+          continue;
+        }
       }
-      if (!std::isfinite(h[1])) throw Error{TS_EBREAKDOWN, "inner CG breakdown: residual is not finite"};
-      if (std::sqrt(h[1]) <= P->opt.inner_tol || inner_total >= P->opt.max_iter) break;
+      fresh = false;
       vcycle_op<float>(P, G, rin, z);
       dot_op<float, float>(P, rin, z, K, sb);
       hip_check(launch_p_update<float>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
       std::swap(sa, sb);
     }
-    // alpha += ||r|| * delta
-    hip_check(launch_axpy_conv<float, double>(dl, alpha, K, 1.0, P->slot(kRR64), st), "update");
-    ++refine;
   }
-  info->iterations = inner_total;
-  info->refinements = refine;
+  info->iterations = total;
+  info->refinements = updates;
   info->rel_residual = rel;
   info->converged = rel <= tol;
   return info->converged ? TS_OK : TS_ENOTCONV;

@@ -43,6 +43,42 @@ class ts_solve_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ts_server_options(ctypes.Structure):
+    _fields_ = [("memory_budget", ctypes.c_size_t), ("slots", ctypes.c_int)]
+
+
+class ts_request(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("q", ctypes.c_int),
+                ("intervals", ctypes.POINTER(ctypes.c_int32)),
+                ("lo", ctypes.POINTER(ctypes.c_double)), ("hi", ctypes.POINTER(ctypes.c_double)),
+                ("n", ctypes.c_int64),
+                ("x", ctypes.POINTER(ctypes.c_double)), ("y", ctypes.POINTER(ctypes.c_double)),
+                ("lam", ctypes.c_double), ("opt", ctypes.POINTER(ts_options))]
+
+
+class ts_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("info", ts_solve_info), ("K", ctypes.c_int64),
+                ("footprint", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("error", ctypes.c_char * 256)]
+
+    def as_dict(self):
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("info", "error")}
+        out["info"] = self.info.as_dict()
+        out["error"] = self.error.decode(errors="replace")
+        return out
+
+
+class ts_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("active", ctypes.c_int), ("max_active", ctypes.c_int),
+                ("in_use", ctypes.c_size_t), ("max_in_use", ctypes.c_size_t),
+                ("memory_budget", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class TsmgError(RuntimeError):
     def __init__(self, status, message):
         super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, message))
@@ -78,6 +114,16 @@ _SIGNATURES = {
     "ts_solve": (_I, [_P, _P, _I, ctypes.POINTER(ts_solve_info)]),
     "ts_evaluate": (_I, [_P, _P, _I64, _P, _P]),
     "ts_profile_apply": (_I, [_P, _I, _I, _I, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "ts_memory": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "ts_footprint": (_I, [_I, _I, ctypes.POINTER(ctypes.c_int32), _I64, ctypes.POINTER(ts_options),
+                          ctypes.POINTER(ctypes.c_size_t)]),
+    "ts_server_default_options": (None, [ctypes.POINTER(ts_server_options)]),
+    "ts_server_create": (_I, [ctypes.POINTER(ts_server_options), ctypes.POINTER(_P)]),
+    "ts_server_submit": (_I, [_P, ctypes.POINTER(ts_request), ctypes.POINTER(ctypes.c_uint64)]),
+    "ts_server_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(_I)]),
+    "ts_server_wait": (_I, [_P, ctypes.c_uint64, _P, _I64, ctypes.POINTER(ts_result)]),
+    "ts_server_get_stats": (_I, [_P, ctypes.POINTER(ts_server_stats)]),
+    "ts_server_destroy": (None, [_P]),
 }
 
 
@@ -235,7 +281,127 @@ def ts_profile_apply(h, level, fp32, reps):
     return a.value, b.value
 
 
-# --- convenience wrapper ---------------------------------------------------
+def ts_memory(h):
+    """(resident, peak) device bytes of a problem."""
+    r, p = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load_library().ts_memory(h, ctypes.byref(r), ctypes.byref(p)))
+    return r.value, p.value
+
+
+def ts_footprint(d, q, intervals, n, opt=None):
+    iv = (ctypes.c_int32 * d)(*[int(v) for v in intervals])
+    b = ctypes.c_size_t()
+    _check(load_library().ts_footprint(int(d), int(q), iv, int(n), ctypes.byref(opt) if opt is not None else None,
+                                       ctypes.byref(b)))
+    return b.value
+
+
+def ts_server_default_options():
+    o = ts_server_options()
+    load_library().ts_server_default_options(ctypes.byref(o))
+    return o
+
+
+def ts_server_create(opt=None):
+    h = _P()
+    _check(load_library().ts_server_create(ctypes.byref(opt) if opt is not None else None, ctypes.byref(h)))
+    return h.value
+
+
+def ts_server_submit(s, req):
+    t = ctypes.c_uint64()
+    _check(load_library().ts_server_submit(s, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def ts_server_poll(s, ticket):
+    done = _I()
+    _check(load_library().ts_server_poll(s, ctypes.c_uint64(ticket), ctypes.byref(done)))
+    return bool(done.value)
+
+
+def ts_server_wait(s, ticket, alpha, capacity):
+    """alpha: host buffer address (int) or None; returns the ts_result."""
+    res = ts_result()
+    _check(load_library().ts_server_wait(s, ctypes.c_uint64(ticket), alpha, int(capacity), ctypes.byref(res)))
+    return res
+
+
+def ts_server_get_stats(s):
+    st = ts_server_stats()
+    _check(load_library().ts_server_get_stats(s, ctypes.byref(st)))
+    return st
+
+
+def ts_server_destroy(s):
+    load_library().ts_server_destroy(s)
+
+
+# --- convenience wrappers --------------------------------------------------
+
+class Server:
+    """Serving loop on the current GPU: submit numpy requests, wait for numpy
+    solutions. Requests are copied at submit; solutions come back as float64
+    arrays of K = (N + 3)^d coefficients (C order)."""
+
+    def __init__(self, memory_budget=0, slots=4):
+        o = ts_server_default_options()
+        o.memory_budget = int(memory_budget)
+        o.slots = int(slots)
+        self.handle = ts_server_create(o)
+        self._K = {}
+
+    def submit(self, x, y, N, lam, lo=None, hi=None, options=None, **opts):
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        n, d = x.shape
+        if y.shape != (n,):
+            raise ValueError("y must have shape (n,)")
+        lo = [0.0] * d if lo is None else lo
+        hi = [1.0] * d if hi is None else hi
+        opt = options if options is not None else ts_default_options()
+        for k, v in opts.items():
+            setattr(opt, k, v)
+        iv = (ctypes.c_int32 * d)(*([int(N)] * d))
+        lo_ = (ctypes.c_double * d)(*[float(v) for v in lo])
+        hi_ = (ctypes.c_double * d)(*[float(v) for v in hi])
+        req = ts_request(d=d, q=3, intervals=iv, lo=lo_, hi=hi_, n=n,
+                         x=x.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         y=y.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                         lam=float(lam), opt=ctypes.pointer(opt))
+        t = ts_server_submit(self.handle, req)
+        self._K[t] = (int(N) + 3) ** d
+        return t
+
+    def poll(self, ticket):
+        return ts_server_poll(self.handle, ticket)
+
+    def wait(self, ticket):
+        """(alpha or None if the request failed, result dict)."""
+        import numpy as np
+        K = self._K.get(ticket)
+        if K is None:     # unknown here: let the library report it
+            ts_server_wait(self.handle, ticket, None, 0)
+        alpha = np.empty(K, dtype=np.float64)
+        res = ts_server_wait(self.handle, ticket, alpha.ctypes.data, K)
+        del self._K[ticket]
+        return (alpha if res.status >= 0 else None), res.as_dict()
+
+    def stats(self):
+        return ts_server_get_stats(self.handle).as_dict()
+
+    def close(self):
+        if self.handle is not None:
+            ts_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
 
 class Smoother:
     """One smoothing problem on the current GPU, outputs as torch tensors.

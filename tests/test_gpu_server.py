@@ -1,0 +1,152 @@
+"""GPU tests of the serving loop through the C ABI: every request solved in a
+mix of concurrent requests gives the result it gives alone (within the
+mixed-precision tolerance), both match the oracle's direct solution, the
+admission respects the memory budget, the footprint estimate bounds the
+memory a problem really takes, and a failing request fails alone."""
+import numpy as np
+import pytest
+
+import gpu_cases as gc
+from oracle import system
+from paper_1901_00654_amd import tsmg, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    """Small requests of the serving recipe (d in 2..4, uniform points,
+    log-uniform lambda), sized for the oracle's direct solve."""
+    reqs = []
+    for i in range(8):
+        r = workloads.serving_request(i, n=int(np.random.default_rng(900 + i).integers(4000, 12000)))
+        r["N"] = {2: 16, 3: 8, 4: 4}[r["d"]]
+        r["lam"] = max(r["lam"], 1e-3)
+        reqs.append(r)
+    return reqs
+
+
+def _opts(precision, tol):
+    o = tsmg.ts_default_options()
+    o.precision = precision
+    o.tol = tol
+    o.max_iter = 20000
+    return o
+
+
+def _direct(r):
+    """Direct solution, kappa(A) and Phi of the request (oracle)."""
+    import scipy.sparse.linalg as spla
+    A, b, Phi, _ = system.system(r["x"], r["y"], r["lo"], r["hi"], r["N"], r["lam"])
+    return spla.spsolve(A.tocsc(), b), np.linalg.cond(A.toarray()), Phi
+
+
+def _rel(Phi, a, ref):
+    return np.linalg.norm(Phi @ (a - ref)) / np.linalg.norm(Phi @ ref)
+
+
+@pytest.fixture(scope="module")
+def reqs(lib):
+    return _requests()
+
+
+def _serve(reqs, slots, precision, tol, one_at_a_time=False, budget=0):
+    S = tsmg.Server(memory_budget=budget, slots=slots)
+    try:
+        out = [None] * len(reqs)
+        if one_at_a_time:
+            for i, r in enumerate(reqs):
+                t = S.submit(r["x"], r["y"], r["N"], r["lam"], r["lo"], r["hi"], options=_opts(precision, tol))
+                out[i] = S.wait(t)
+        else:
+            ts = [S.submit(r["x"], r["y"], r["N"], r["lam"], r["lo"], r["hi"], options=_opts(precision, tol))
+                  for r in reqs]
+            for i, t in enumerate(ts):
+                out[i] = S.wait(t)
+        return out, S.stats()
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("precision,tol,bound", [(tsmg.TS_MIXED_FP32, 1e-10, 1e-6), (tsmg.TS_FP64, 1e-12, 1e-9)])
+def test_mix_equals_alone_and_oracle(reqs, precision, tol, bound):
+    """Fitted values within `bound` (the precision mode's tolerance) alone, in
+    the mix and against the direct solution; coefficients within the bound
+    the conditioning allows (kappa(A) reaches 1e12 where corner B-splines
+    barely meet the box)."""
+    alone, _ = _serve(reqs, 1, precision, tol, one_at_a_time=True)
+    mix, st = _serve(reqs, 4, precision, tol)
+    assert st["max_active"] > 1, st        # the requests really shared the device
+    assert st["completed"] == len(reqs) and st["failed"] == 0, st
+    for i, r in enumerate(reqs):
+        a1, res1 = alone[i]
+        a2, res2 = mix[i]
+        print("request", i, "d", r["d"], "N", r["N"], "n", len(r["y"]), "lam", r["lam"], res2["info"], flush=True)
+        assert res1["status"] == tsmg.TS_OK and res2["status"] == tsmg.TS_OK, (res1, res2)
+        assert res2["info"]["rel_residual"] <= tol
+        ref, kappa, Phi = _direct(r)
+        assert _rel(Phi, a2, a1) <= bound, i
+        assert _rel(Phi, a2, ref) <= bound and _rel(Phi, a1, ref) <= bound, i
+        cbound = max(bound, 10 * tol * kappa)
+        assert np.linalg.norm(a2 - ref) <= cbound * np.linalg.norm(ref), (i, kappa)
+        assert np.linalg.norm(a2 - a1) <= cbound * np.linalg.norm(ref), (i, kappa)
+        assert res2["t_submit"] <= res2["t_start"] <= res2["t_done"]
+
+
+def test_admission_respects_budget(reqs):
+    fps = [tsmg.ts_footprint(r["d"], 3, [r["N"]] * r["d"], len(r["y"])) for r in reqs]
+    budget = int(2.2 * max(fps)) + (64 << 20)
+    out, st = _serve(reqs, 8, tsmg.TS_MIXED_FP32, 1e-8, budget=budget)
+    assert st["max_in_use"] <= budget, st
+    assert st["completed"] == len(reqs)
+    for a, res in out:
+        assert res["status"] == tsmg.TS_OK and res["footprint"] <= budget
+        assert res["peak_bytes"] <= res["footprint"], res
+
+
+@pytest.mark.parametrize("name", ["c1", "c2s", "c3s", "u5"])
+def test_footprint_bounds_measured_memory(lib, name):
+    w = {"c1": lambda: gc.case("c1", 10000, 32), "c2s": lambda: gc.case("c2", 20011, 16),
+         "c3s": lambda: gc.case("c3", 8009, 8), "u5": lambda: gc.uniform_case(5, 2503, 4, 1e-3, 5)}[name]()
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"])
+    try:
+        resident, peak = tsmg.ts_memory(S.handle)
+        est = tsmg.ts_footprint(w["d"], 3, [w["N"]] * w["d"], len(w["y"]))
+        print(name, "resident", resident, "peak", peak, "estimate", est, flush=True)
+        assert 0 < resident <= peak <= est
+        assert est <= 3 * peak + (64 << 20)     # an estimate, not a blanket reservation
+    finally:
+        S.close()
+
+
+def test_failing_request_fails_alone(reqs):
+    S = tsmg.Server(slots=3)
+    try:
+        good = [S.submit(r["x"], r["y"], r["N"], r["lam"], r["lo"], r["hi"], options=_opts(tsmg.TS_FP64, 1e-8))
+                for r in reqs[:3]]
+        r = reqs[0]
+        bad_x = r["x"].copy()
+        bad_x[7, 0] = r["hi"][0] + 1.0          # a point outside the box
+        bad = S.submit(bad_x, r["y"], r["N"], r["lam"], r["lo"], r["hi"])
+        a, res = S.wait(bad)
+        assert a is None and res["status"] == tsmg.TS_EINVAL and "outside" in res["error"]
+        for t in good:
+            a, res = S.wait(t)
+            assert res["status"] == tsmg.TS_OK and a is not None
+        with pytest.raises(tsmg.TsmgError) as e:
+            S.wait(bad)                          # released ticket
+        assert e.value.status == tsmg.TS_EINVAL
+        st = S.stats()
+        assert st["failed"] == 1 and st["completed"] == 3
+    finally:
+        S.close()
+
+
+def test_request_larger_than_budget_is_refused(reqs):
+    S = tsmg.Server(memory_budget=1 << 20, slots=1)
+    try:
+        r = reqs[0]
+        with pytest.raises(tsmg.TsmgError) as e:
+            S.submit(r["x"], r["y"], r["N"], r["lam"], r["lo"], r["hi"])
+        assert e.value.status == tsmg.TS_ENOMEM
+    finally:
+        S.close()

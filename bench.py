@@ -34,6 +34,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_data_c2.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1901_00654_amd", "csrc", "kernels.hip")
 
 
+SERVE_PRECISION = {"mixed": lambda t: t.TS_MIXED_FP32, "vcycle32": lambda t: t.TS_MIXED_FP32_VCYCLE}
+PRECISIONS_BY_CODE = {0: "fp64", 1: "mixed (FP32 CG, reliable FP64 updates)",
+                      3: "vcycle32 (FP64 CG, FP32 V-cycle)"}
+
+
 def algorithmic(d, n, K, fp32):
     """FLOP and bytes one point pass must spend: per point the d*4 cubic values
     (15 d FLOP), the tensor product (4^d), gather (2 * 4^d) and scatter
@@ -132,6 +137,69 @@ def apply_rate(tsmg, torch, w, stream, reps):
     return out
 
 
+def serving(tsmg, workloads, R, slots, served_precision):
+    """The serving trace (first R requests): plain FP64 one request at a time,
+    then a mixed-precision mode through the serving loop with Poisson arrivals
+    at twice the measured FP64 capacity. Both to a relative FP64 true residual
+    of 1e-8."""
+    import numpy as np
+    reqs = [workloads.serving_request(i) for i in range(R)]
+
+    def opts(prec):
+        o = tsmg.ts_default_options()
+        o.precision = prec
+        o.tol = 1e-8
+        o.max_iter = 200000
+        return o
+
+    def summary(results, span):
+        lat = np.array([res["t_done"] - res["t_submit"] for _, res in results])
+        return {"solves_per_s": len(results) / span, "span_s": span,
+                "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                "max_rel_residual": max(res["info"]["rel_residual"] for _, res in results),
+                "failed": sum(res["status"] != tsmg.TS_OK for _, res in results)}
+
+    S = tsmg.Server(slots=1)
+    seq = []
+    try:
+        for r in reqs:
+            t = S.submit(r["x"], r["y"], r["N"], r["lam"], options=opts(tsmg.TS_FP64))
+            seq.append(S.wait(t))
+    finally:
+        S.close()
+    span_seq = max(res["t_done"] for _, res in seq) - min(res["t_submit"] for _, res in seq)
+    out = {"requests": R, "sample": "requests 0..%d of the serving trace (d in 2..4, N in 16..64, "
+                                    "n log-uniform 1e4..1e6, lambda log-uniform 1e-6..1e-2)" % (R - 1),
+           "fp64_sequential": summary(seq, span_seq)}
+    rate = 2.0 * R / span_seq
+    arrivals = workloads.poisson_arrivals(R, rate)
+    S = tsmg.Server(slots=slots)
+    try:
+        t0 = time.perf_counter()
+        tickets = []
+        for i, r in enumerate(reqs):
+            delay = t0 + arrivals[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(S.submit(r["x"], r["y"], r["N"], r["lam"], options=opts(served_precision)))
+        mixed = [S.wait(t) for t in tickets]
+        st = S.stats()
+    finally:
+        S.close()
+    span = max(res["t_done"] for _, res in mixed) - min(res["t_submit"] for _, res in mixed)
+    m = summary(mixed, span)
+    m.update({"precision": PRECISIONS_BY_CODE[served_precision], "slots": slots,
+              "arrival_rate_per_s": rate, "max_active": st["max_active"],
+              "max_in_use_bytes": st["max_in_use"]})
+    out["mixed_served"] = m
+    out["max_rel_diff_alpha_mixed_vs_fp64"] = max(
+        float(np.linalg.norm(a2 - a1) / np.linalg.norm(a1)) for (a1, _), (a2, _) in zip(seq, mixed)
+        if a1 is not None and a2 is not None)
+    out["iterations_fp64"] = [res["info"]["iterations"] for _, res in seq]
+    out["iterations_mixed"] = [res["info"]["iterations"] for _, res in mixed]
+    return out
+
+
 def copy_calibration(torch):
     """A plain streaming kernel of known size (1 GiB read, 1 GiB written, as
     an elementwise multiply by one, which runs as a kernel where a same-type
@@ -180,6 +248,13 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the d=2..5 apply sweep")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests of the serving trace to run (0: skip the serving leg)")
+    ap.add_argument("--serve-slots", type=int, default=4, help="concurrent solves in the serving loop")
+    ap.add_argument("--serve-precision", choices=["mixed", "vcycle32"], default="vcycle32",
+                    help="mode of the served requests: FP32 CG with reliable updates, or FP64 CG "
+                         "with an FP32 V-cycle")
+    ap.add_argument("--only-serve", action="store_true", help="run only the serving leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--only-apply", default=None, metavar="WORKLOAD",
@@ -198,6 +273,10 @@ def main():
     tsmg.load_library()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.only_serve:
+        print(json.dumps(serving(tsmg, workloads, args.serve_requests, args.serve_slots,
+                                 SERVE_PRECISION[args.serve_precision](tsmg))), flush=True)
+        return
     if args.only_apply:
         wk = workloads.CONFIGS[args.only_apply]()
         res = apply_rate(tsmg, torch, wk, stream, args.reps)
@@ -266,6 +345,10 @@ def main():
             sweep.append(apply_rate(tsmg, torch, wk, stream, args.reps))
             torch.cuda.empty_cache()
         result["apply_sweep"] = sweep
+
+    if args.serve_requests > 0:
+        result["serving"] = serving(tsmg, workloads, args.serve_requests, args.serve_slots,
+                                    SERVE_PRECISION[args.serve_precision](tsmg))
 
     if args.copy_calibration:
         result["copy_calibration_bytes"] = copy_calibration(torch)

@@ -67,9 +67,14 @@ typedef enum {
                              FP64 solution and the FP32 residual replaced by the FP64
                              true residual each time it has dropped by inner_tol
                              (iterative refinement that keeps the search direction) */
-    TS_MIXED_BF16 = 2     /* reserved: bfloat16 storage of the per-point 1D basis values
+    TS_MIXED_BF16 = 2,    /* reserved: bfloat16 storage of the per-point 1D basis values
                              of the inner operator; not available in this version
                              (TS_EINVAL)                                              */
+    TS_MIXED_FP32_VCYCLE = 3  /* Alg. 8 in FP64 (recurrences, operator applies, inner
+                             products) with the V-cycle preconditioner in FP32 on the
+                             normalised residual and the flexible (Polak-Ribiere)
+                             direction update; iteration counts follow FP64 even
+                             where kappa(A) is beyond single precision             */
 } ts_precision;
 
 typedef struct {

@@ -92,7 +92,7 @@ ts_status ts_set_options(ts_problem* p, const ts_options* opt) {
   need(opt != nullptr, "opt must not be null");
   need(opt->nu1 >= 0 && opt->nu2 >= 0, "nu1, nu2 must be >= 0");
   need(opt->tol > 0.0 && opt->max_iter >= 0 && opt->max_refine >= 0, "tol must be > 0, limits >= 0");
-  need(opt->precision == TS_FP64 || opt->precision == TS_MIXED_FP32, "unknown or unavailable precision");
+  need(tsmg::precision_available(opt->precision), "unknown or unavailable precision");
   P->opt.nu1 = opt->nu1;
   P->opt.nu2 = opt->nu2;
   P->opt.precision = opt->precision;

@@ -735,6 +735,24 @@ __global__ __launch_bounds__(kBlock) void k_p_update(T* p, const T* z, int64_t K
   p[k] = T(double(z[k]) + beta * double(p[k]));
 }
 
+// Flexible (Polak-Ribiere) direction update p = z + beta p with
+// beta = ((*num) - (*sub)) / (*den).
+__global__ __launch_bounds__(kBlock) void k_p_update_flex(double* p, const double* z, int64_t K, const double* num,
+                                                          const double* sub, const double* den) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  const double beta = (*num - *sub) / *den;
+  p[k] = z[k] + beta * p[k];
+}
+
+// y = (*smul)^(1/2) * x with conversion.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void k_scale_mul(const TI* x, TO* y, int64_t K, const double* smul) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  y[k] = TO(sqrt(*smul) * double(x[k]));
+}
+
 // y = s * x with conversion; s = scale * (*sden)^(-1/2) when sden is given.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(kBlock) void k_scale_copy(const TI* x, TO* y, int64_t K, double scale,
@@ -1346,6 +1364,17 @@ hipError_t launch_p_update(T* p, const T* z, int64_t K, const double* num, const
 }
 template hipError_t launch_p_update<double>(double*, const double*, int64_t, const double*, const double*, hipStream_t);
 template hipError_t launch_p_update<float>(float*, const float*, int64_t, const double*, const double*, hipStream_t);
+
+hipError_t launch_p_update_flex(double* p, const double* z, int64_t K, const double* num, const double* sub,
+                               const double* den, hipStream_t st) {
+  hipLaunchKernelGGL(k_p_update_flex, dim3(blocks_for(K)), dim3(kBlock), 0, st, p, z, K, num, sub, den);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_mul(const float* x, double* y, int64_t K, const double* smul, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_mul<float, double>), dim3(blocks_for(K)), dim3(kBlock), 0, st, x, y, K, smul);
+  return hipGetLastError();
+}
 
 template <typename TI, typename TO>
 hipError_t launch_scale_copy(const TI* x, TO* y, int64_t K, double scale, const double* sden, hipStream_t st) {

@@ -57,6 +57,11 @@ template <typename T>
 hipError_t launch_p_update(T* p, const T* z, int64_t K, const double* num, const double* den, hipStream_t st);
 template <typename TI, typename TO>
 hipError_t launch_scale_copy(const TI* x, TO* y, int64_t K, double scale, const double* sden, hipStream_t st);
+// p = z + ((*num) - (*sub)) / (*den) p (flexible CG direction update)
+hipError_t launch_p_update_flex(double* p, const double* z, int64_t K, const double* num, const double* sub,
+                               const double* den, hipStream_t st);
+// y = sqrt(*smul) x
+hipError_t launch_scale_mul(const float* x, double* y, int64_t K, const double* smul, hipStream_t st);
 template <typename TI, typename TO>
 hipError_t launch_axpy_conv(const TI* x, TO* y, int64_t K, double scale, const double* smul, hipStream_t st);
 

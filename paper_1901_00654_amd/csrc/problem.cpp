@@ -653,7 +653,7 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     ts_default_options(&P->opt);
     if (opt) P->opt = *opt;
     if (P->opt.nu1 < 0 || P->opt.nu2 < 0) throw Error{TS_EINVAL, "nu1, nu2 must be >= 0"};
-    if (P->opt.precision != TS_FP64 && P->opt.precision != TS_MIXED_FP32)
+    if (!precision_available(P->opt.precision))
       throw Error{TS_EINVAL, "unknown or unavailable precision"};
     if (!(P->opt.tol > 0.0)) throw Error{TS_EINVAL, "tol must be > 0"};
     if (P->opt.omega_fixed <= 0.0 && !(P->opt.omega_scale > 0.0 && P->opt.omega_scale < 2.0))

@@ -16,6 +16,11 @@ struct Error {
 };
 
 void hip_check(hipError_t e, const char* what);
+
+// Precision modes this build solves in (TS_MIXED_BF16 is reserved).
+inline bool precision_available(int p) {
+  return p == TS_FP64 || p == TS_MIXED_FP32 || p == TS_MIXED_FP32_VCYCLE;
+}
 void set_error(const std::string& m);
 
 // Device bytes held by DevBuf objects allocated on this thread (live) and

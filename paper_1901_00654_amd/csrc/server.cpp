@@ -238,7 +238,7 @@ ts_status ts_server_submit(ts_server* s, const ts_request* q, uint64_t* ticket) 
   ts_default_options(&r->opt);
   if (q->opt) r->opt = *q->opt;
   r->opt.stream = nullptr;
-  need(r->opt.precision == TS_FP64 || r->opt.precision == TS_MIXED_FP32, "unknown or unavailable precision");
+  need(tsmg::precision_available(r->opt.precision), "unknown or unavailable precision");
   need(r->opt.tol > 0.0, "tol must be > 0");
   r->n = q->n;
   r->lam = q->lambda;

@@ -13,7 +13,7 @@ namespace tsmg {
 
 namespace {
 
-enum Slot : int { kScratch = 0, kBB = 1, kRZa = 2, kRZb = 3, kPV = 4, kRR = 5, kRR64 = 6 };
+enum Slot : int { kScratch = 0, kBB = 1, kRZa = 2, kRZb = 3, kPV = 4, kRR = 5, kRR64 = 6, kRZo = 7 };
 
 void rhs_into(Problem* P, double* b) {
   const int64_t K = P->lev[P->G].K;
@@ -48,7 +48,25 @@ bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
 void rhs_op(Problem* P, double* b) { rhs_into(P, b); }
 
-static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_info* info) {
+// z = B r with the V-cycle in FP64, or (pc32) in FP32 on r / ||r|| with the
+// result scaled back; slot rr holds ||r||^2.
+static void precondition(Problem* P, bool pc32, const double* r, double* z, int rr) {
+  const int G = P->G;
+  const int64_t K = P->lev[G].K;
+  if (!pc32) {
+    vcycle_op<double>(P, G, r, z);
+    return;
+  }
+  hip_check(launch_scale_copy<double, float>(r, P->r32.p, K, 1.0, P->slot(rr), P->stream), "to fp32");
+  vcycle_op<float>(P, G, P->r32.p, P->z32.p);
+  hip_check(launch_scale_mul(P->z32.p, z, K, P->slot(rr), P->stream), "to fp64");
+}
+
+// Alg. 8 in FP64. With pc32 the V-cycle runs in FP32 and the direction
+// update takes the flexible form beta = r'(z - z_old) / r_old'z_old, which
+// tolerates the rounding of the preconditioner; the Krylov recurrences and
+// every operator apply stay FP64.
+static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_info* info, bool pc32 = false) {
   const int G = P->G;
   const int64_t K = P->lev[G].K;
   hipStream_t st = P->stream;
@@ -76,7 +94,8 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
   double rel_true = 1.0;
   for (;;) {
     int sa = kRZa, sb = kRZb;
-    vcycle_op<double>(P, G, r, z);
+    if (pc32) dot_op<double, double>(P, r, r, K, kRR);
+    precondition(P, pc32, r, z, kRR);
     hip_check(launch_scale_copy<double, double>(z, p, K, 1.0, nullptr, st), "copy");
     dot_op<double, double>(P, r, z, K, sa);
     while (total < P->opt.max_iter) {
@@ -90,9 +109,11 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
       if (!finite_pos(h[0]) || !std::isfinite(h[1]))
         throw Error{TS_EBREAKDOWN, "CG breakdown: p'Ap = " + std::to_string(h[0])};
       if (std::sqrt(h[1]) / bnorm <= tol) break;
-      vcycle_op<double>(P, G, r, z);
+      if (pc32) dot_op<double, double>(P, r, z, K, kRZo);   // r_new' z_old
+      precondition(P, pc32, r, z, kRR);
       dot_op<double, double>(P, r, z, K, sb);
-      hip_check(launch_p_update<double>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
+      if (pc32) hip_check(launch_p_update_flex(p, z, K, P->slot(sb), P->slot(kRZo), P->slot(sa), st), "p update");
+      else hip_check(launch_p_update<double>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
       std::swap(sa, sb);
     }
     // confirm with the true FP64 residual; restart from it if the recursive
@@ -217,6 +238,7 @@ ts_status solve(Problem* P, double* alpha, int use_start, ts_solve_info* info_ou
   const int64_t applies0 = P->applies;
   ts_status s;
   if (P->opt.precision == TS_FP64) s = solve_fp64(P, alpha, use_start, &info);
+  else if (P->opt.precision == TS_MIXED_FP32_VCYCLE) s = solve_fp64(P, alpha, use_start, &info, true);
   else s = solve_mixed(P, alpha, use_start, &info);
   hip_check(hipStreamSynchronize(P->stream), "sync");
   info.setup_s = P->setup_s;

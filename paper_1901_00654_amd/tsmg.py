@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtsmg.so")
 
 TS_OK, TS_ENOTCONV, TS_EINVAL, TS_ENOMEM, TS_EDEVICE, TS_ESINGULAR, TS_EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
-TS_FP64, TS_MIXED_FP32, TS_MIXED_BF16 = 0, 1, 2
+TS_FP64, TS_MIXED_FP32, TS_MIXED_BF16, TS_MIXED_FP32_VCYCLE = 0, 1, 2, 3
 TS_STENCIL_AUTO, TS_STENCIL_NONE, TS_STENCIL_ALL = 0, 1, 2
 _STATUS = {0: "TS_OK", 1: "TS_ENOTCONV", -1: "TS_EINVAL", -2: "TS_ENOMEM", -3: "TS_EDEVICE",
            -4: "TS_ESINGULAR", -5: "TS_EBREAKDOWN"}

@@ -32,7 +32,7 @@ def test_apply_sampled_entries(full):
     assert gc.rel(out[ks], ref) < 1e-12
 
 
-@pytest.mark.parametrize("precision", [tsmg.TS_FP64, tsmg.TS_MIXED_FP32])
+@pytest.mark.parametrize("precision", [tsmg.TS_FP64, tsmg.TS_MIXED_FP32, tsmg.TS_MIXED_FP32_VCYCLE])
 def test_solve_true_residual(full, precision):
     w, S = full
     if w["name"] in ("c3", "c4"):

@@ -67,7 +67,8 @@ def _serve(reqs, slots, precision, tol, one_at_a_time=False, budget=0):
         S.close()
 
 
-@pytest.mark.parametrize("precision,tol,bound", [(tsmg.TS_MIXED_FP32, 1e-10, 1e-6), (tsmg.TS_FP64, 1e-12, 1e-9)])
+@pytest.mark.parametrize("precision,tol,bound", [(tsmg.TS_MIXED_FP32, 1e-10, 1e-6), (tsmg.TS_FP64, 1e-12, 1e-9),
+                                                 (tsmg.TS_MIXED_FP32_VCYCLE, 1e-10, 1e-6)])
 def test_mix_equals_alone_and_oracle(reqs, precision, tol, bound):
     """Fitted values within `bound` (the precision mode's tolerance) alone, in
     the mix and against the direct solution; coefficients within the bound

@@ -95,10 +95,11 @@ def test_solve_fp64_matches_direct(both):
     assert _check_solution(M, alpha, ref, lev, 1e-10) < 100 * tol
 
 
-def test_solve_mixed_matches_direct(both):
+@pytest.mark.parametrize("precision", [tsmg.TS_MIXED_FP32, tsmg.TS_MIXED_FP32_VCYCLE])
+def test_solve_mixed_matches_direct(both, precision):
     w, S, M = both
     ref, lev = _direct(w, M)
-    alpha, status, info = _solve_with(S, tol=1e-10, precision=tsmg.TS_MIXED_FP32)
+    alpha, status, info = _solve_with(S, tol=1e-10, precision=precision)
     if M.kappa >= 1e15:
         # numerically singular in FP64: single precision sees an indefinite
         # matrix, and the refinement may stop short of 1e-10
@@ -106,7 +107,8 @@ def test_solve_mixed_matches_direct(both):
         assert info["rel_residual"] < 1e-6, info
         return
     assert status == tsmg.TS_OK, info
-    assert info["refinements"] >= 1
+    if precision == tsmg.TS_MIXED_FP32:
+        assert info["refinements"] >= 1
     assert _check_solution(M, alpha, ref, lev, 1e-6) < 1e-9
 
 
@@ -119,6 +121,22 @@ def test_iterations_match_oracle(both):
     # rounding differences shift long CG runs on ill-conditioned systems
     slack = 0.03 if M.kappa <= 1e10 else 0.10
     assert abs(info["iterations"] - it_oracle) <= max(2, slack * it_oracle), (info, it_oracle)
+    assert info["rel_residual"] <= 1e-8
+
+
+def test_fp32_vcycle_mode_keeps_fp64_iterations(both):
+    """FP64 Krylov with an FP32 V-cycle: the flexible update absorbs the
+    preconditioner's rounding, so the iteration count follows FP64."""
+    w, S, M = both
+    if M.kappa >= 1e15:
+        pytest.skip("numerically singular case")
+    _, st64, info64 = _solve_with(S, tol=1e-8)
+    _, st, info = _solve_with(S, tol=1e-8, precision=tsmg.TS_MIXED_FP32_VCYCLE)
+    assert st64 == tsmg.TS_OK and st == tsmg.TS_OK, (info64, info)
+    it64 = info64["iterations"]
+    # long runs on very ill-conditioned systems feel the FP32 rounding more
+    slack = 0.05 if M.kappa <= 1e10 else 0.25
+    assert abs(info["iterations"] - it64) <= max(2, slack * it64), (info64, info)
     assert info["rel_residual"] <= 1e-8
 
 

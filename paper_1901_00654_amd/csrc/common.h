@@ -11,6 +11,9 @@ constexpr int kBlock = 256;      // threads per workgroup for every kernel
 // Most sorted points one workgroup of the point pass takes, by dimension
 // (bounded by the LDS that stages them).
 constexpr int kMaxPointsPerBlock[kMaxDim + 1] = {0, 2048, 2048, 1024, 1024, 512};
+// Tile side 2^kTileBits[d] cells per dimension in the point pass (levels with
+// fewer cells use the whole grid as one tile).
+constexpr int kTileBits[kMaxDim + 1] = {0, 6, 4, 2, 1, 1};
 
 // What the point pass of the data term computes (Alg. 3/4/5):
 enum DataMode : int {

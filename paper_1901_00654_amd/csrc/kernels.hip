@@ -196,6 +196,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* wave_sums, int* 
   return before + x - v;
 }
 
+constexpr int kMaxTileCells = 256;   // cells of one tile, at most (one per thread)
+
 template <int D>
 struct Group {
   static constexpr int L = (D <= 2) ? 1 : (1 << (2 * (D - 2)));   // lanes per item
@@ -203,10 +205,9 @@ struct Group {
   static constexpr int Q = (D <= 2) ? 16 : (D == 3 ? 8 : (D == 4 ? 16 : 32));   // points per item
   static constexpr int NG = kBlock / L;                            // groups per workgroup
   static constexpr int PPB = kMaxPointsPerBlock[D];                // points per workgroup, at most
-  static constexpr int MAXI = PPB / Q + 256;                       // items per tile segment, at most
+  static constexpr int MAXI = PPB / Q + kMaxTileCells;             // items per tile segment, at most
   static constexpr bool STAGE_C = D <= 4;                          // coefficient patch in LDS
 };
-constexpr int kMaxTileCells = 256;
 
 // Polynomial coefficients (t^0..t^3) of the cubic piece b_a on one interval.
 template <typename T>
@@ -317,7 +318,9 @@ __host__ __device__ constexpr size_t lacc_offset(int patch) {
   return (MODE == kApply && STAGE_C) ? ((size_t(patch) * sizeof(T) + 15) & ~size_t(15)) : 0;
 }
 
-template <int D, typename T, int MODE>
+// TBF >= 0: the tile side is 2^TBF (known at compile time, the usual case);
+// TBF < 0: it is a.tb (levels coarser than one full tile).
+template <int D, typename T, int MODE, int TBF>
 __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   using GP = Group<D>;
   constexpr int L = GP::L;
@@ -335,7 +338,8 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   __shared__ T s_tt[D][PPB];   // level-g position of each point of the segment in its cell
 
   T* lc = reinterpret_cast<T*>(smem_raw);
-  const int Tg = 1 << a.tb;
+  const int tbits = TBF >= 0 ? TBF : a.tb;
+  const int Tg = 1 << tbits;
   const int P = Tg + kDeg;
   int patch = 1;
 #pragma unroll
@@ -354,8 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   const uint32_t maskN = (1u << a.G) - 1u;
   const uint32_t maskSh = (1u << sh) - 1u;
   const T scale = T(1.0) / T(double(1u << sh));   // exact power of two
-  const int S = D * (sh + a.tb);                  // finest Morton key -> tile index
-  const int cells_in_tile = 1 << (D * a.tb);
+  const int S = D * (sh + tbits);                  // finest Morton key -> tile index
+  const int cells_in_tile = 1 << (D * tbits);
   const T* tfrac = reinterpret_cast<const T*>(a.tfrac);
   const T* cin = reinterpret_cast<const T*>(a.c);
   T* out = reinterpret_cast<T*>(a.out);
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     const int64_t seg_end = min(end, int64_t(a.off[size_t(tile + 1) << S]));
     if (seg_end <= pos) break;   // offsets are monotone with off[N^D] = n; never taken
     int org[D];
-    morton_decode<D>(tile, a.g - a.tb, org);
+    morton_decode<D>(tile, a.g - tbits, org);
 #pragma unroll
     for (int p = 0; p < D; ++p) org[p] *= Tg;
 
@@ -387,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     // thread j owns cell j of the tile (cells_in_tile <= kBlock)
     int nch = 0, cnt = 0, lo_rel = 0;
     if (int(threadIdx.x) < cells_in_tile) {
-      const size_t gc = (size_t(tile) << (D * a.tb)) + size_t(threadIdx.x);
+      const size_t gc = (size_t(tile) << (D * tbits)) + size_t(threadIdx.x);
       int64_t lo = a.off[gc << (D * sh)], hi = a.off[(gc + 1) << (D * sh)];
       lo = max(lo, pos);
       hi = min(hi, seg_end);
@@ -435,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     for (int it = grp; it < n_items; it += GP::NG) {
       const int j = it_cell[it];
       int cl[D];
-      morton_decode<D>(uint32_t(j), a.tb, cl);
+      morton_decode<D>(uint32_t(j), tbits, cl);
       int base = lead_off;
 #pragma unroll
       for (int p = 0; p < D; ++p) base += cl[p] * st[p];
@@ -464,29 +468,10 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       }
       const int l0 = it_lo[it];
       const int l1 = l0 + it_cnt[it];
-      // two points per step: independent chains for the scheduler to interleave
-      int li = l0;
-      for (; li + 1 < l1; li += 2) {
-        PointVals<D, T> q0, q1;
-        point_basis<D, T, NLEAD>(s_tt, li, hc, q0);
-        point_basis<D, T, NLEAD>(s_tt, li + 1, hc, q1);
-        T s0, s1;
-        if constexpr (MODE == kApply) {
-          const T g0 = q0.w * point_gather<D, T>(q0, cv);
-          const T g1 = q1.w * point_gather<D, T>(q1, cv);
-          s0 = group_sum<T, L>(g0);
-          s1 = group_sum<T, L>(g1);
-        } else if constexpr (MODE == kRhs) {
-          s0 = T(a.y[pos + li]);
-          s1 = T(a.y[pos + li + 1]);
-        } else {
-          s0 = T(1);
-          s1 = T(1);
-        }
-        point_scatter<D, T, MODE == kDiag>(q0, s0, acc);
-        point_scatter<D, T, MODE == kDiag>(q1, s1, acc);
-      }
-      if (li < l1) {
+      // one point per step: the live registers stay low enough for five
+      // (d = 3) or four (d = 4, 5) waves per SIMD, which hides the LDS and
+      // DPP latencies better than two interleaved points at three waves
+      for (int li = l0; li < l1; ++li) {
         PointVals<D, T> q0;
         point_basis<D, T, NLEAD>(s_tt, li, hc, q0);
         T s0;
@@ -1233,8 +1218,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int3
 // Host launchers.
 static inline unsigned blocks_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
-template <int D, typename T, int MODE>
-static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
+template <int D, typename T, int MODE, int TBF>
+static hipError_t launch_data_tb(const DataArgs& a, hipStream_t st) {
   const int Tg = 1 << a.tb;
   int patch = 1;
   for (int p = 0; p < D; ++p) patch *= (Tg + kDeg);
@@ -1243,12 +1228,18 @@ static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
   const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
   if (grid == 0) return hipSuccess;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE, TBF>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_data<D, T, MODE>), dim3(grid), dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((k_data<D, T, MODE, TBF>), dim3(grid), dim3(kBlock), lds, st, a);
   return hipGetLastError();
+}
+
+template <int D, typename T, int MODE>
+static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
+  if (a.tb == kTileBits[D]) return launch_data_tb<D, T, MODE, kTileBits[D]>(a, st);
+  return launch_data_tb<D, T, MODE, -1>(a, st);
 }
 
 template <typename T, int MODE>

@@ -407,14 +407,6 @@ template void dot_op<float, float>(Problem*, const float*, const float*, int64_t
 
 // ---------------------------------------------------------------------------
 // Setup.
-static int tile_bits_for(int D) {
-  switch (D) {
-    case 1: return 6;
-    case 2: return 4;
-    case 3: return 2;
-    default: return 1;
-  }
-}
 
 static void compute_diag(Problem* P, int g) {
   Level& L = P->lev[g];
@@ -716,7 +708,7 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     if (P->opt.points_per_block > 0) {
       P->ppb = std::max(64, std::min(ppb_max, P->opt.points_per_block));
     } else {
-      int64_t ppb = (n + 4095) / 4096;
+      int64_t ppb = (n + 8191) / 8192;   // about 8192 workgroups
       ppb = ((ppb + 63) / 64) * 64;
       P->ppb = int(std::max<int64_t>(std::min(256, ppb_max), std::min<int64_t>(ppb_max, ppb)));
     }
@@ -731,7 +723,7 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
       L.J = L.N + kDeg;
       L.K = 1;
       for (int p = 0; p < d; ++p) L.K *= L.J;
-      L.tb = std::min(tile_bits_for(d), g);
+      L.tb = std::min(kTileBits[d], g);
       std::vector<double> band(size_t(d) * 3 * L.J * 7);
       for (int p = 0; p < d; ++p) {
         std::vector<double> b1;

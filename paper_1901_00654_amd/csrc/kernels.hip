@@ -646,6 +646,108 @@ __global__ __launch_bounds__(kBlock) void k_restrict_pass(TransferArgs<T> a) {
 
 // ---------------------------------------------------------------------------
 // Jacobi smoother and residual epilogues (Alg. 6, Alg. 7).
+// All d dimensions of a transfer in one kernel, for small levels where the
+// pass-per-dimension form is launch-bound. Per dimension each output takes
+// up to 5 (restriction) or 3 (prolongation) inputs; idx holds their flat
+// offsets (stride included) and wt their weights (0 for indices that fall
+// off the grid, whose offset is then 0).
+template <int D, int P, int M, typename T>
+struct TensorGather {
+  static __device__ __forceinline__ T sum(const T* in, const T* sub, const int64_t (&idx)[D][M],
+                                          const T (&wt)[D][M], int64_t off) {
+    T v = T(0);
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+      if (wt[P][m] != T(0)) v += wt[P][m] * TensorGather<D, P + 1, M, T>::sum(in, sub, idx, wt, off + idx[P][m]);
+    return v;
+  }
+};
+template <int D, int M, typename T>
+struct TensorGather<D, D, M, T> {
+  static __device__ __forceinline__ T sum(const T* in, const T* sub, const int64_t (&)[D][M], const T (&)[D][M],
+                                          int64_t off) {
+    return sub ? in[off] - sub[off] : in[off];
+  }
+};
+
+// out (coarse, Jc^D) = (I_{g-1}^g)' (in - sub) (sub may be null). Each coarse
+// entry gathers 5^D fine entries; 32 lanes share them and sum by shuffles,
+// 8 coarse entries per workgroup.
+constexpr int kRestrictLanes = 32;
+
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict_fused(const T* in, const T* sub, T* out, int Jc, int Jf,
+                                                           int64_t Kc) {
+  constexpr int NT = (D == 1) ? 5 : (D == 2 ? 25 : (D == 3 ? 125 : 625));
+  const int lane = threadIdx.x % kRestrictLanes;
+  const int64_t k = int64_t(blockIdx.x) * (kBlock / kRestrictLanes) + threadIdx.x / kRestrictLanes;
+  int j[D];
+  {
+    int64_t rem = k < Kc ? k : 0;
+#pragma unroll
+    for (int p = D - 1; p >= 0; --p) {
+      j[p] = int(rem % Jc);
+      rem /= Jc;
+    }
+  }
+  T v = T(0);
+  if (k < Kc) {
+    for (int t = lane; t < NT; t += kRestrictLanes) {
+      int rem = t;
+      int64_t off = 0;
+      T w = T(1);
+      bool ok = true;
+#pragma unroll
+      for (int p = D - 1; p >= 0; --p) {
+        const int m = rem % 5;
+        rem /= 5;
+        const int i = 2 * j[p] - 3 + m;
+        ok = ok && i >= 0 && i < Jf;
+        w *= (m == 0 || m == 4) ? T(0.125) : (m == 2 ? T(0.75) : T(0.5));
+        int64_t stride = 1;
+#pragma unroll
+        for (int q = p + 1; q < D; ++q) stride *= Jf;
+        off += int64_t(i) * stride;
+      }
+      if (ok) v += w * (sub ? in[off] - sub[off] : in[off]);
+    }
+  }
+#pragma unroll
+  for (int m = kRestrictLanes / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  if (lane == 0 && k < Kc) out[k] = v;
+}
+
+// out (fine, Jf^D) = I_{g-1}^g e, or out -= I_{g-1}^g e when subtract is set.
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong_fused(const T* e, T* out, int Jc, int Jf, int64_t Kf,
+                                                          int subtract) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= Kf) return;
+  int64_t idx[D][3];
+  T wt[D][3];
+  int64_t rem = k, stride = 1;
+#pragma unroll
+  for (int p = D - 1; p >= 0; --p) {
+    const int i = int(rem % Jf);
+    rem /= Jf;
+    const int mm = i >> 1;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const int j = mm + m;
+      T w;
+      if (i & 1) w = (m == 1) ? T(0.75) : T(0.125);
+      else w = (m == 2) ? T(0) : T(0.5);
+      const bool ok = j < Jc && w != T(0);
+      wt[p][m] = ok ? w : T(0);
+      idx[p][m] = ok ? int64_t(j) * stride : 0;
+    }
+    stride *= Jc;
+  }
+  const T v = TensorGather<D, 0, 3, T>::sum(e, static_cast<const T*>(nullptr), idx, wt, 0);
+  if (subtract) out[k] -= v;
+  else out[k] = v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K) {
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -1170,9 +1272,31 @@ __global__ __launch_bounds__(kBlock) void k_stencil_finalize(const double* inter
 // whose first-dimension offset is `plane`, and the 7 plane sums are added in
 // LDS. A neighbour outside the grid has S = 0; its index is clamped into range
 // so the (finite) value read there is multiplied by zero.
-enum StencilEpilogue : int { kStPlain = 0, kStJacobi = 1, kStResidual = 2 };
+enum StencilEpilogue : int { kStPlain = 0, kStJacobi = 1, kStResidual = 2, kStJacobiZero = 3 };
 constexpr int kStRows = kBlock / 7;   // 36 rows per block
 
+// Input value at flat index i: x[i], or for kStJacobiZero the first sweep
+// from zero, w[i] b[i] (x is not read).
+template <typename T, int EPI>
+__device__ __forceinline__ T stencil_in(const T* x, const T* b, const T* w, int64_t i) {
+  if constexpr (EPI == kStJacobiZero) return w[i] * b[i];
+  else return x[i];
+}
+
+template <typename T, int EPI>
+__device__ __forceinline__ void stencil_out(const T* x, T* out, const T* b, const T* w, int64_t k, T v) {
+  if constexpr (EPI == kStPlain) out[k] = v;
+  else if constexpr (EPI == kStJacobi) out[k] = x[k] + w[k] * (b[k] - v);
+  else if constexpr (EPI == kStResidual) out[k] = v - b[k];
+  else {
+    const T x1 = w[k] * b[k];
+    out[k] = x1 + w[k] * (b[k] - v);
+  }
+}
+
+// Rows k of the level in blocks of 36; each of the 7 first-dimension offset
+// planes of a row (7^(D-1) stencil points each) is one thread; the planes
+// are summed in LDS. For levels with many rows (streams the stencil once).
 template <typename T, int D, int EPI>
 __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int32_t* offs, const T* x, T* out,
                                                           const T* b, const T* w, int64_t K) {
@@ -1191,14 +1315,14 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int3
         int64_t i0 = k + offs[o0], i1 = k + offs[o1];
         i0 = i0 < 0 ? 0 : (i0 >= K ? K - 1 : i0);
         i1 = i1 < 0 ? 0 : (i1 >= K ? K - 1 : i1);
-        a0 += S[int64_t(o0) * K + k] * x[i0];
-        a1 += S[int64_t(o1) * K + k] * x[i1];
+        a0 += S[int64_t(o0) * K + k] * stencil_in<T, EPI>(x, b, w, i0);
+        a1 += S[int64_t(o1) * K + k] * stencil_in<T, EPI>(x, b, w, i1);
       }
       if (j < NI) {
         const int o0 = obase + j;
         int64_t i0 = k + offs[o0];
         i0 = i0 < 0 ? 0 : (i0 >= K ? K - 1 : i0);
-        a0 += S[int64_t(o0) * K + k] * x[i0];
+        a0 += S[int64_t(o0) * K + k] * stencil_in<T, EPI>(x, b, w, i0);
       }
     }
     part[plane][rl] = a0 + a1;
@@ -1208,10 +1332,47 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int3
     T v = T(0);
 #pragma unroll
     for (int q = 0; q < 7; ++q) v += part[q][threadIdx.x];
-    if constexpr (EPI == kStPlain) out[k] = v;
-    else if constexpr (EPI == kStJacobi) out[k] = x[k] + w[k] * (b[k] - v);
-    else out[k] = v - b[k];
+    stencil_out<T, EPI>(x, out, b, w, k, v);
   }
+}
+
+// The same product for levels with few rows, where the kernel above is
+// latency-bound (49 or more dependent iterations per thread): 8 rows per
+// block, 32 threads per row, each taking every 32nd stencil point, summed by
+// a tree in LDS.
+constexpr int kStSmallRows = 8;
+constexpr int kStSmallCols = kBlock / kStSmallRows;
+constexpr int64_t kStSmallMaxK = 16384;
+
+template <typename T, int D, int EPI>
+__global__ __launch_bounds__(kBlock) void k_stencil_apply_small(const T* S, const int32_t* offs, const T* x, T* out,
+                                                                const T* b, const T* w, int64_t K) {
+  constexpr int NO = (D == 1) ? 7 : (D == 2 ? 49 : (D == 3 ? 343 : (D == 4 ? 2401 : 16807)));
+  constexpr int PER = (NO + kStSmallCols - 1) / kStSmallCols;
+  __shared__ T part[kStSmallCols][kStSmallRows];
+  const int r = threadIdx.x % kStSmallRows;
+  const int c = threadIdx.x / kStSmallRows;
+  const int64_t k = int64_t(blockIdx.x) * kStSmallRows + r;
+  T a = T(0);
+  if (k < K) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int o = c + q * kStSmallCols;
+      if (o < NO) {
+        int64_t i = k + offs[o];
+        i = i < 0 ? 0 : (i >= K ? K - 1 : i);
+        a += S[int64_t(o) * K + k] * stencil_in<T, EPI>(x, b, w, i);
+      }
+    }
+  }
+  part[c][r] = a;
+  __syncthreads();
+#pragma unroll
+  for (int h = kStSmallCols / 2; h >= 1; h >>= 1) {
+    if (c < h) part[c][r] += part[c + h][r];
+    __syncthreads();
+  }
+  if (c == 0 && k < K) stencil_out<T, EPI>(x, out, b, w, k, part[0][r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1297,6 +1458,43 @@ hipError_t launch_transfer(bool prolong, const TransferArgs<T>& a, hipStream_t s
 }
 template hipError_t launch_transfer<double>(bool, const TransferArgs<double>&, hipStream_t);
 template hipError_t launch_transfer<float>(bool, const TransferArgs<float>&, hipStream_t);
+
+template <typename T, int D>
+static hipError_t launch_transfer_fused_d(bool prolong, const T* in, const T* sub, T* out, int Jc, int Jf,
+                                          int subtract, hipStream_t st) {
+  int64_t Kc = 1, Kf = 1;
+  for (int p = 0; p < D; ++p) { Kc *= Jc; Kf *= Jf; }
+  if (prolong) {
+    hipLaunchKernelGGL((k_prolong_fused<D, T>), dim3(blocks_for(Kf)), dim3(kBlock), 0, st, in, out, Jc, Jf, Kf,
+                       subtract);
+  } else if constexpr (D <= 4) {
+    const int per_block = kBlock / kRestrictLanes;
+    hipLaunchKernelGGL((k_restrict_fused<D, T>), dim3(unsigned((Kc + per_block - 1) / per_block)), dim3(kBlock), 0,
+                       st, in, sub, out, Jc, Jf, Kc);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transfer_fused(int D, bool prolong, const T* in, const T* sub, T* out, int Jc, int Jf,
+                                 int subtract, hipStream_t st) {
+  switch (D) {
+    case 1: return launch_transfer_fused_d<T, 1>(prolong, in, sub, out, Jc, Jf, subtract, st);
+    case 2: return launch_transfer_fused_d<T, 2>(prolong, in, sub, out, Jc, Jf, subtract, st);
+    case 3: return launch_transfer_fused_d<T, 3>(prolong, in, sub, out, Jc, Jf, subtract, st);
+    case 4: return launch_transfer_fused_d<T, 4>(prolong, in, sub, out, Jc, Jf, subtract, st);
+    case 5:
+      if (!prolong) return hipErrorInvalidValue;   // restriction at d = 5 runs pass by pass
+      return launch_transfer_fused_d<T, 5>(prolong, in, sub, out, Jc, Jf, subtract, st);
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_transfer_fused<double>(int, bool, const double*, const double*, double*, int, int, int,
+                                                  hipStream_t);
+template hipError_t launch_transfer_fused<float>(int, bool, const float*, const float*, float*, int, int, int,
+                                                 hipStream_t);
 
 template <typename T>
 hipError_t launch_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K, hipStream_t st) {
@@ -1563,6 +1761,18 @@ hipError_t launch_stencil_finalize(int D, const double* inter, const double* ban
 template <typename T, int EPI>
 static hipError_t launch_stencil_epi(int D, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
                                      const T* w, int64_t K, hipStream_t st) {
+  if (K <= kStSmallMaxK) {
+    const unsigned gs = unsigned((K + kStSmallRows - 1) / kStSmallRows);
+    switch (D) {
+      case 1: hipLaunchKernelGGL((k_stencil_apply_small<T, 1, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+      case 2: hipLaunchKernelGGL((k_stencil_apply_small<T, 2, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+      case 3: hipLaunchKernelGGL((k_stencil_apply_small<T, 3, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+      case 4: hipLaunchKernelGGL((k_stencil_apply_small<T, 4, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+      case 5: hipLaunchKernelGGL((k_stencil_apply_small<T, 5, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const unsigned g = unsigned((K + kStRows - 1) / kStRows);
   switch (D) {
     case 1: hipLaunchKernelGGL((k_stencil_apply<T, 1, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
@@ -1581,7 +1791,9 @@ hipError_t launch_stencil_apply(int D, int epi, const T* S, const int32_t* offs,
   if (K == 0) return hipSuccess;
   if (epi == kStPlain) return launch_stencil_epi<T, kStPlain>(D, S, offs, x, out, b, w, K, st);
   if (epi == kStJacobi) return launch_stencil_epi<T, kStJacobi>(D, S, offs, x, out, b, w, K, st);
-  return launch_stencil_epi<T, kStResidual>(D, S, offs, x, out, b, w, K, st);
+  if (epi == kStResidual) return launch_stencil_epi<T, kStResidual>(D, S, offs, x, out, b, w, K, st);
+  if (epi == kStJacobiZero) return launch_stencil_epi<T, kStJacobiZero>(D, S, offs, x, out, b, w, K, st);
+  return hipErrorInvalidValue;
 }
 template hipError_t launch_stencil_apply<double>(int, int, const double*, const int32_t*, const double*, double*,
                                                  const double*, const double*, int64_t, hipStream_t);

@@ -42,6 +42,12 @@ template <typename T> hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipS
 hipError_t launch_lambda_diag(int D, const double* band, int J, int64_t K, double lam, double* out,
                               hipStream_t st);
 template <typename T> hipError_t launch_transfer(bool prolong, const TransferArgs<T>& a, hipStream_t st);
+// Whole transfer in one kernel (small levels): prolongation out (=|-=) I in,
+// or restriction out = I'(in - sub) (sub may be null).
+template <typename T>
+hipError_t launch_transfer_fused(int D, bool prolong, const T* in, const T* sub, T* out, int Jc, int Jf,
+                                 int subtract, hipStream_t st);
+constexpr int64_t kFusedTransferMaxK = 65536;   // fine-level size up to which the fused form is used
 
 template <typename T> hipError_t launch_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K, hipStream_t st);
 template <typename T> hipError_t launch_jacobi(T* alpha, const T* wdinv, const T* b, const T* Ax, int64_t K,
@@ -97,7 +103,9 @@ hipError_t launch_stencil_pass(const double* in, double* out, const double* ctab
                                int64_t inner, hipStream_t st);
 hipError_t launch_stencil_finalize(int D, const double* inter, const double* band, int J, int64_t K, double lam,
                                    double* S64, float* S32, hipStream_t st);
-// epi: 0 out = A x; 1 out = x + w (b - A x); 2 out = A x - b (out must not alias x)
+// epi: 0 out = A x; 1 out = x + w (b - A x); 2 out = A x - b; 3 two Jacobi sweeps
+// from zero, out = x1 + w (b - A x1) with x1 = w b (x unused). out must not
+// alias x, b or w.
 template <typename T>
 hipError_t launch_stencil_apply(int D, int epi, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
                                 const T* w, int64_t K, hipStream_t st);

@@ -221,6 +221,11 @@ template <typename T>
 void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract) {
   const int D = P->d;
   const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
+  if (P->lev[g].K <= kFusedTransferMaxK) {
+    hip_check(launch_transfer_fused<T>(D, true, e, nullptr, out, Jc, Jf, subtract ? 1 : 0, P->stream),
+              "prolongation");
+    return;
+  }
   T* X = prob_xfer<T>(P);
   T* bufs[2] = {X, X + P->lev[P->G].K};
   const T* in = e;
@@ -248,6 +253,10 @@ template <typename T>
 void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub) {
   const int D = P->d;
   const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
+  if (P->lev[g].K <= kFusedTransferMaxK && D <= 4) {   // (d = 5 would keep its gather tables in scratch)
+    hip_check(launch_transfer_fused<T>(D, false, r, sub, out, Jc, Jf, 0, P->stream), "restriction");
+    return;
+  }
   T* X = prob_xfer<T>(P);
   T* bufs[2] = {X, X + P->lev[P->G].K};
   const T* in = r;
@@ -302,17 +311,21 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
   if (L.stencil) {
     // Jacobi sweeps fused into the stencil product, ping-ponging between
     // alpha and t; the first sweep lands so that the last one ends in alpha.
+    // (the first two sweeps from zero are one fused product)
     const T* S = lvl_S<T>(L);
-    const int swaps = std::max(0, nu1 - 1) + nu2;
+    const int swaps = std::max(0, nu1 - 2) + nu2;
     T* cur = (swaps % 2 == 0) ? alpha : t;
     T* oth = (cur == alpha) ? t : alpha;
-    if (nu1 >= 1) {
-      hip_check(launch_jacobi_first<T>(cur, w, b, K, P->stream), "jacobi");
-      for (int j = 1; j < nu1; ++j) {
+    if (nu1 >= 2) {
+      hip_check(launch_stencil_apply<T>(P->d, 3, S, L.soffs.p, nullptr, cur, b, w, K, P->stream), "jacobi");
+      P->applies++;
+      for (int j = 2; j < nu1; ++j) {
         hip_check(launch_stencil_apply<T>(P->d, 1, S, L.soffs.p, cur, oth, b, w, K, P->stream), "jacobi");
         P->applies++;
         std::swap(cur, oth);
       }
+    } else if (nu1 == 1) {
+      hip_check(launch_jacobi_first<T>(cur, w, b, K, P->stream), "jacobi");
     } else {
       hip_check(launch_fill<T>(cur, T(0), K, P->stream), "fill");
     }

@@ -36,6 +36,15 @@ struct DataArgs {
   int g;                    // this level
   int tb;                   // tile side 2^tb level-g cells per dimension (tb <= g)
   int ppb;                  // points per workgroup (<= kMaxPointsPerBlock[d])
+  // Optional work list of this level (built once at setup; null: the kernel
+  // derives the same segments and items from mkey and off on the fly):
+  const int32_t* wl_first;  // [workgroups + 1] first segment of each workgroup
+  const int4* wl_segs;      // [segments + 1] {first point, end point, tile, first item}
+  const uint32_t* wl_items; // [items] cell in tile | first point - segment start << 8 | count << 20
 };
+
+// Packing of one work-list item (a cell's run of at most Q points).
+constexpr int kItemLoShift = 8;
+constexpr int kItemCntShift = 20;
 
 }  // namespace tsmg

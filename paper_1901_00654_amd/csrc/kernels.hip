@@ -319,8 +319,10 @@ __host__ __device__ constexpr size_t lacc_offset(int patch) {
 }
 
 // TBF >= 0: the tile side is 2^TBF (known at compile time, the usual case);
-// TBF < 0: it is a.tb (levels coarser than one full tile).
-template <int D, typename T, int MODE, int TBF>
+// TBF < 0: it is a.tb (levels coarser than one full tile). WL: take the
+// segments and items from the level's precomputed work list instead of
+// deriving them from the sorted keys and cell offsets.
+template <int D, typename T, int MODE, int TBF, bool WL>
 __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   using GP = Group<D>;
   constexpr int L = GP::L;
@@ -376,12 +378,35 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     lead_off += aq * st[q];
   }
 
-  int64_t pos = int64_t(xcd_block()) * a.ppb;
-  const int64_t end = min(a.n, pos + int64_t(a.ppb));
-  while (pos < end) {
-    const uint32_t tile = a.mkey[pos] >> S;
-    const int64_t seg_end = min(end, int64_t(a.off[size_t(tile + 1) << S]));
-    if (seg_end <= pos) break;   // offsets are monotone with off[N^D] = n; never taken
+  const int wg = xcd_block();
+  int64_t pos = 0, end = 0;
+  int s_cur = 0, s_end = 0;
+  if constexpr (WL) {
+    s_cur = a.wl_first[wg];
+    s_end = a.wl_first[wg + 1];
+  } else {
+    pos = int64_t(wg) * a.ppb;
+    end = min(a.n, pos + int64_t(a.ppb));
+  }
+  for (;;) {
+    uint32_t tile;
+    int64_t seg_end;
+    int item_b = 0, item_e = 0;
+    if constexpr (WL) {
+      if (s_cur >= s_end) break;
+      const int4 sd = a.wl_segs[s_cur];
+      pos = sd.x;
+      seg_end = sd.y;
+      tile = uint32_t(sd.z);
+      item_b = sd.w;
+      item_e = a.wl_segs[s_cur + 1].w;
+      ++s_cur;
+    } else {
+      if (pos >= end) break;
+      tile = a.mkey[pos] >> S;
+      seg_end = min(end, int64_t(a.off[size_t(tile + 1) << S]));
+      if (seg_end <= pos) break;   // offsets are monotone with off[N^D] = n; never taken
+    }
     int org[D];
     morton_decode<D>(tile, a.g - tbits, org);
 #pragma unroll
@@ -390,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     // per-cell point ranges of this segment, cut into items of <= Q points;
     // thread j owns cell j of the tile (cells_in_tile <= kBlock)
     int nch = 0, cnt = 0, lo_rel = 0;
-    if (int(threadIdx.x) < cells_in_tile) {
+    if (!WL && int(threadIdx.x) < cells_in_tile) {
       const size_t gc = (size_t(tile) << (D * tbits)) + size_t(threadIdx.x);
       int64_t lo = a.off[gc << (D * sh)], hi = a.off[(gc + 1) << (D * sh)];
       lo = max(lo, pos);
@@ -425,19 +450,35 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       }
       lacc[e] = 0.0;
     }
-    int n_items_all;
-    const int first = block_exclusive_scan(nch, scan_sh, &n_items_all);
-    // first + k < PPB / Q + kMaxTileCells = MAXI (the host keeps ppb <= PPB)
-    for (int k = 0; k < nch && first + k < MAXI; ++k) {
-      it_cell[first + k] = int(threadIdx.x);
-      it_lo[first + k] = lo_rel + k * Q;
-      it_cnt[first + k] = min(Q, cnt - k * Q);
+    int n_items = 0;
+    if constexpr (WL) {
+      n_items = item_e - item_b;
+      __syncthreads();
+    } else {
+      int n_items_all;
+      const int first = block_exclusive_scan(nch, scan_sh, &n_items_all);
+      // first + k < PPB / Q + kMaxTileCells = MAXI (the host keeps ppb <= PPB)
+      for (int k = 0; k < nch && first + k < MAXI; ++k) {
+        it_cell[first + k] = int(threadIdx.x);
+        it_lo[first + k] = lo_rel + k * Q;
+        it_cnt[first + k] = min(Q, cnt - k * Q);
+      }
+      __syncthreads();
+      n_items = min(n_items_all, MAXI);
     }
-    __syncthreads();
-    const int n_items = min(n_items_all, MAXI);
 
     for (int it = grp; it < n_items; it += GP::NG) {
-      const int j = it_cell[it];
+      int j, l0, l1;
+      if constexpr (WL) {
+        const uint32_t w = a.wl_items[item_b + it];
+        j = int(w & 0xFFu);
+        l0 = int((w >> kItemLoShift) & 0xFFFu);
+        l1 = l0 + int(w >> kItemCntShift);
+      } else {
+        j = it_cell[it];
+        l0 = it_lo[it];
+        l1 = l0 + it_cnt[it];
+      }
       int cl[D];
       morton_decode<D>(uint32_t(j), tbits, cl);
       int base = lead_off;
@@ -466,8 +507,6 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
         if constexpr (MODE == kApply && STAGE_C) cv[v] = lc[base + off];
         acc[v] = T(0);
       }
-      const int l0 = it_lo[it];
-      const int l1 = l0 + it_cnt[it];
       // one point per step: the live registers stay low enough for five
       // (d = 3) or four (d = 4, 5) waves per SIMD, which hides the LDS and
       // DPP latencies better than two interleaved points at three waves
@@ -503,7 +542,64 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       }
     }
     __syncthreads();
+    if constexpr (!WL) pos = seg_end;
+  }
+}
+
+// Work list of the point pass of one level (setup): the same tile segments
+// and items the pass derives on the fly, per logical workgroup. PASS 0 counts
+// segments and items per workgroup; PASS 1 writes them at the offsets given
+// by the exclusive scans seg_base / item_base of those counts.
+template <int D, int TBF, int PASS>
+__global__ __launch_bounds__(kBlock) void k_worklist(DataArgs a, int32_t* seg_count, int32_t* item_count,
+                                                     const int32_t* seg_base, const int32_t* item_base,
+                                                     int4* segs, uint32_t* items) {
+  constexpr int Q = Group<D>::Q;
+  __shared__ int scan_sh[kBlock / 64];
+  const int tbits = TBF >= 0 ? TBF : a.tb;
+  const int sh = a.G - a.g;
+  const int S = D * (sh + tbits);
+  const int cells_in_tile = 1 << (D * tbits);
+  const int wg = blockIdx.x;
+  int64_t pos = int64_t(wg) * a.ppb;
+  const int64_t end = min(a.n, pos + int64_t(a.ppb));
+  int nseg = 0, nitem = 0;
+  int sb = 0, ib = 0;
+  if constexpr (PASS == 1) {
+    sb = seg_base[wg];
+    ib = item_base[wg];
+  }
+  while (pos < end) {
+    const uint32_t tile = a.mkey[pos] >> S;
+    const int64_t seg_end = min(end, int64_t(a.off[size_t(tile + 1) << S]));
+    if (seg_end <= pos) break;
+    int nch = 0, cnt = 0, lo_rel = 0;
+    if (int(threadIdx.x) < cells_in_tile) {
+      const size_t gc = (size_t(tile) << (D * tbits)) + size_t(threadIdx.x);
+      int64_t lo = a.off[gc << (D * sh)], hi = a.off[(gc + 1) << (D * sh)];
+      lo = max(lo, pos);
+      hi = min(hi, seg_end);
+      cnt = hi > lo ? int(hi - lo) : 0;
+      lo_rel = int(lo - pos);
+      nch = (cnt + Q - 1) / Q;
+    }
+    int total;
+    const int first = block_exclusive_scan(nch, scan_sh, &total);
+    if constexpr (PASS == 1) {
+      for (int k = 0; k < nch; ++k)
+        items[ib + nitem + first + k] = uint32_t(threadIdx.x) | (uint32_t(lo_rel + k * Q) << kItemLoShift) |
+                                        (uint32_t(min(Q, cnt - k * Q)) << kItemCntShift);
+      if (threadIdx.x == 0) segs[sb + nseg] = make_int4(int(pos), int(seg_end), int(tile), ib + nitem);
+    }
+    ++nseg;
+    nitem += total;
     pos = seg_end;
+  }
+  if constexpr (PASS == 0) {
+    if (threadIdx.x == 0) {
+      seg_count[wg] = nseg;
+      item_count[wg] = nitem;
+    }
   }
 }
 
@@ -1379,7 +1475,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply_small(const T* S, cons
 // Host launchers.
 static inline unsigned blocks_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
-template <int D, typename T, int MODE, int TBF>
+template <int D, typename T, int MODE, int TBF, bool WL>
 static hipError_t launch_data_tb(const DataArgs& a, hipStream_t st) {
   const int Tg = 1 << a.tb;
   int patch = 1;
@@ -1389,18 +1485,61 @@ static hipError_t launch_data_tb(const DataArgs& a, hipStream_t st) {
   const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
   if (grid == 0) return hipSuccess;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE, TBF>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE, TBF, WL>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_data<D, T, MODE, TBF>), dim3(grid), dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((k_data<D, T, MODE, TBF, WL>), dim3(grid), dim3(kBlock), lds, st, a);
   return hipGetLastError();
 }
 
 template <int D, typename T, int MODE>
 static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
-  if (a.tb == kTileBits[D]) return launch_data_tb<D, T, MODE, kTileBits[D]>(a, st);
-  return launch_data_tb<D, T, MODE, -1>(a, st);
+  if constexpr (MODE == kApply) {
+    if (a.wl_items) {
+      if (a.tb == kTileBits[D]) return launch_data_tb<D, T, MODE, kTileBits[D], true>(a, st);
+      return launch_data_tb<D, T, MODE, -1, true>(a, st);
+    }
+  }
+  if (a.tb == kTileBits[D]) return launch_data_tb<D, T, MODE, kTileBits[D], false>(a, st);
+  return launch_data_tb<D, T, MODE, -1, false>(a, st);
+}
+
+template <int D, int TBF>
+static hipError_t launch_worklist_tb(int pass, const DataArgs& a, int32_t* seg_count, int32_t* item_count,
+                                     const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
+                                     hipStream_t st) {
+  const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
+  if (grid == 0) return hipSuccess;
+  if (pass == 0)
+    hipLaunchKernelGGL((k_worklist<D, TBF, 0>), dim3(grid), dim3(kBlock), 0, st, a, seg_count, item_count, seg_base,
+                       item_base, segs, items);
+  else
+    hipLaunchKernelGGL((k_worklist<D, TBF, 1>), dim3(grid), dim3(kBlock), 0, st, a, seg_count, item_count, seg_base,
+                       item_base, segs, items);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t launch_worklist_d(int pass, const DataArgs& a, int32_t* seg_count, int32_t* item_count,
+                                    const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
+                                    hipStream_t st) {
+  if (a.tb == kTileBits[D])
+    return launch_worklist_tb<D, kTileBits[D]>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
+  return launch_worklist_tb<D, -1>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
+}
+
+hipError_t launch_worklist(int D, int pass, const DataArgs& a, int32_t* seg_count, int32_t* item_count,
+                           const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
+                           hipStream_t st) {
+  switch (D) {
+    case 1: return launch_worklist_d<1>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
+    case 2: return launch_worklist_d<2>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
+    case 3: return launch_worklist_d<3>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
+    case 4: return launch_worklist_d<4>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
+    case 5: return launch_worklist_d<5>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int MODE>

@@ -190,7 +190,52 @@ static DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out
   a.g = g;
   a.tb = L.tb;
   a.ppb = P->ppb;
+  if (L.wl_items.p) {
+    a.wl_first = L.wl_first.p;
+    a.wl_segs = L.wl_segs.p;
+    a.wl_items = L.wl_items.p;
+  }
   return a;
+}
+
+// Work list of the point pass on level g: segments and items per workgroup,
+// counted, scanned on the host and written on the device.
+static void build_worklist(Problem* P, int g) {
+  Level& L = P->lev[g];
+  hipStream_t st = P->stream;
+  DataArgs a = data_args(P, g, false, nullptr, nullptr);
+  a.wl_first = nullptr;
+  a.wl_segs = nullptr;
+  a.wl_items = nullptr;
+  const int64_t nwg = (P->n + P->ppb - 1) / P->ppb;
+  DevBuf<int32_t> cnt, ibase;
+  cnt.alloc(size_t(2 * nwg));
+  hip_check(launch_worklist(P->d, 0, a, cnt.p, cnt.p + nwg, nullptr, nullptr, nullptr, nullptr, st), "worklist");
+  std::vector<int32_t> h(static_cast<size_t>(2 * nwg));
+  hip_check(hipMemcpyAsync(h.data(), cnt.p, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st), "download");
+  hip_check(hipStreamSynchronize(st), "sync");
+  std::vector<int32_t> first(static_cast<size_t>(nwg + 1)), ib(static_cast<size_t>(nwg));
+  int64_t nseg = 0, nitem = 0;
+  for (int64_t w = 0; w < nwg; ++w) {
+    first[size_t(w)] = int32_t(nseg);
+    ib[size_t(w)] = int32_t(nitem);
+    nseg += h[size_t(w)];
+    nitem += h[size_t(nwg + w)];
+    if (nseg >= INT32_MAX || nitem >= INT32_MAX) throw Error{TS_EINVAL, "work list exceeds 2^31 entries"};
+  }
+  first[size_t(nwg)] = int32_t(nseg);
+  L.wl_first.alloc(first.size());
+  ibase.alloc(ib.size());
+  L.wl_segs.alloc(size_t(nseg + 1));
+  L.wl_items.alloc(size_t(std::max<int64_t>(nitem, 1)));
+  const int4 sentinel = make_int4(0, 0, 0, int(nitem));
+  hip_check(hipMemcpyAsync(L.wl_first.p, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
+            "upload");
+  hip_check(hipMemcpyAsync(ibase.p, ib.data(), ib.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
+  hip_check(hipMemcpyAsync(L.wl_segs.p + nseg, &sentinel, sizeof(int4), hipMemcpyHostToDevice, st), "upload");
+  hip_check(launch_worklist(P->d, 1, a, nullptr, nullptr, L.wl_first.p, ibase.p, L.wl_segs.p, L.wl_items.p, st),
+            "worklist");
+  hip_check(hipStreamSynchronize(st), "sync");   // host vectors go out of scope
 }
 
 template <typename T> static const T* lvl_S(Level& L);
@@ -561,8 +606,16 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
     const int J = (1 << g) + kDeg;
     const int64_t K = ipow(J, d);
     levels += 56 * K + int64_t(d) * 3 * J * 7 * 12;
+    const bool st = want_stencil(d, J, n, opt.stencil_mode, stencil_budget_for(stencil_budget));
+    if (!st) {   // work list: items <= n, segments <= workgroups + nonempty tiles
+      const int64_t nwg = (n + 255) / 256 + 1;
+      const int tb = std::min(kTileBits[d], g);
+      const int64_t ntiles = int64_t(1) << (d * (g - tb));
+      levels += 8 * (nwg + 1) + 16 * (nwg + std::min(n, ntiles) + 1) + 4 * n;
+      stencil_tmp = std::max(stencil_tmp, 8 * nwg);
+    }
     // level 1 always carries its stencil: A_1 is expanded from it
-    if (g == 1 || want_stencil(d, J, n, opt.stencil_mode, stencil_budget_for(stencil_budget))) {
+    if (g == 1 || st) {
       stencils += ipow(7, d) * K * 12 + ipow(7, d) * 4;
       stencil_tmp = std::max(stencil_tmp, 2 * ipow(7 * int64_t(J), d) * 8 + (1 << 16));
     }
@@ -780,6 +833,10 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
       for (int g = 1; g <= G; ++g)
         if (want_stencil(d, P->lev[g].J, n, P->opt.stencil_mode, budget)) build_stencil(P, g);
     }
+
+    // --- work lists of the point pass on the matrix-free levels
+    for (int g = 1; g <= G; ++g)
+      if (!P->lev[g].stencil) build_worklist(P, g);
 
     // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)
     for (int g = 1; g <= G; ++g) compute_diag(P, g);

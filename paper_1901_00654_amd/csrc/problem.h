@@ -86,6 +86,10 @@ struct Level {
   DevBuf<double> S64;              // [7^d][K] offset-major stencil
   DevBuf<float> S32;
   DevBuf<int32_t> soffs;           // [7^d] flat index offset of each stencil point
+  // work list of the point pass (levels applied matrix-free)
+  DevBuf<int32_t> wl_first;        // [workgroups + 1]
+  DevBuf<int4> wl_segs;            // [segments + 1]
+  DevBuf<uint32_t> wl_items;       // [items]
 };
 
 constexpr int kSlots = 16;

@@ -650,6 +650,155 @@ __global__ __launch_bounds__(kBlock) void k_lambda_pass(LambdaArgs<T> a) {
 
 // lambda * diag(Lambda_g) from the diagonals of the 1D factors; `band` holds
 // [D][3][J][7] (each dimension has its own mesh width).
+// lambda * Lambda c in one kernel for d = 2 and 3: each workgroup computes
+// a tile of the output from a halo-extended tile of c staged in LDS, running
+// the three-accumulator recursion of k_lambda_pass over the dimensions in
+// LDS (out-of-grid halo entries are zero, which drops the same taps the pass
+// form skips). band: d blocks of [3][J][7] (M, G1, G2 per dimension).
+constexpr int kLamB1 = 8;    // d = 3: output rows per tile along dimension 1 (dimension 0: 1 row)
+constexpr int kLamB2 = 32;   // last dimension
+constexpr int kLamH1 = kLamB1 + 6, kLamH2 = kLamB2 + 6;
+
+template <typename T>
+__device__ __forceinline__ void band_row(const T* band, int J, int j, T (&m)[7], T (&g1)[7], T (&g2)[7]) {
+#pragma unroll
+  for (int o = 0; o < 7; ++o) {
+    m[o] = band[size_t(j) * 7 + o];
+    g1[o] = band[size_t(J) * 7 + size_t(j) * 7 + o];
+    g2[o] = band[size_t(2 * J) * 7 + size_t(j) * 7 + o];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* c, T* out, const T* band, int J, int B1, int B2,
+                                                          int nt1, int nt2, T lam) {
+  __shared__ T sin_[7 * kLamH1 * kLamH2];   // staged c; later the dimension-1 results
+  __shared__ T s1[3 * kLamH1 * kLamH2];     // dimension-0 results T0, T1, T2
+  const int t2 = blockIdx.x % nt2;
+  const int t1 = (blockIdx.x / nt2) % nt1;
+  const int j0 = blockIdx.x / (nt2 * nt1);
+  const int H1 = B1 + 6, H2 = B2 + 6;
+  const int b1base = t1 * B1 - 3, b2base = t2 * B2 - 3;
+  const int64_t JJ = int64_t(J) * J;
+  for (int e = threadIdx.x; e < 7 * H1 * H2; e += kBlock) {
+    const int h2 = e % H2, h1 = (e / H2) % H1, o0 = e / (H2 * H1);
+    const int g0 = j0 + o0 - 3, g1 = b1base + h1, g2 = b2base + h2;
+    const bool ok = g0 >= 0 && g0 < J && g1 >= 0 && g1 < J && g2 >= 0 && g2 < J;
+    sin_[e] = ok ? c[int64_t(g0) * JJ + int64_t(g1) * J + g2] : T(0);
+  }
+  __syncthreads();
+  {
+    T m[7], g1c[7], g2c[7];
+    band_row(band, J, j0, m, g1c, g2c);
+    for (int e = threadIdx.x; e < H1 * H2; e += kBlock) {
+      T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+      for (int o = 0; o < 7; ++o) {
+        const T v = sin_[o * H1 * H2 + e];
+        a0 += m[o] * v;
+        a1 += g1c[o] * v;
+        a2 += g2c[o] * v;
+      }
+      s1[e] = a0;
+      s1[H1 * H2 + e] = a1;
+      s1[2 * H1 * H2 + e] = a2;
+    }
+  }
+  __syncthreads();
+  const T* band1 = band + size_t(3) * J * 7;
+  T* s2 = sin_;   // [3][B1][H2]
+  for (int e = threadIdx.x; e < B1 * H2; e += kBlock) {
+    const int h2 = e % H2, b1 = e / H2;
+    const int j1 = t1 * B1 + b1;
+    if (j1 >= J) continue;
+    T m[7], g1c[7], g2c[7];
+    band_row(band1, J, j1, m, g1c, g2c);
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+      const int q = (b1 + o) * H2 + h2;
+      const T v0 = s1[q], v1 = s1[H1 * H2 + q], v2 = s1[2 * H1 * H2 + q];
+      a0 += m[o] * v0;
+      a1 += m[o] * v1 + g1c[o] * v0;
+      a2 += m[o] * v2 + g2c[o] * v0 + T(2) * g1c[o] * v1;
+    }
+    s2[e] = a0;
+    s2[B1 * H2 + e] = a1;
+    s2[2 * B1 * H2 + e] = a2;
+  }
+  __syncthreads();
+  const T* band2 = band + size_t(6) * J * 7;
+  for (int e = threadIdx.x; e < B1 * B2; e += kBlock) {
+    const int b2 = e % B2, b1 = e / B2;
+    const int j1 = t1 * B1 + b1, j2 = t2 * B2 + b2;
+    if (j1 >= J || j2 >= J) continue;
+    T m[7], g1c[7], g2c[7];
+    band_row(band2, J, j2, m, g1c, g2c);
+    T a = T(0);
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+      const int q = b1 * H2 + b2 + o;
+      a += m[o] * s2[2 * B1 * H2 + q] + g2c[o] * s2[q] + T(2) * g1c[o] * s2[B1 * H2 + q];
+    }
+    out[int64_t(j0) * JJ + int64_t(j1) * J + j2] = lam * a;
+  }
+}
+
+constexpr int kLam2B0 = 8, kLam2B1 = 32;
+constexpr int kLam2H0 = kLam2B0 + 6, kLam2H1 = kLam2B1 + 6;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_lambda_fused2(const T* c, T* out, const T* band, int J, int B0, int B1,
+                                                          int nt1, T lam) {
+  __shared__ T sin_[kLam2H0 * kLam2H1];
+  __shared__ T s1[3 * kLam2B0 * kLam2H1];
+  const int t1 = blockIdx.x % nt1;
+  const int t0 = blockIdx.x / nt1;
+  const int H0 = B0 + 6, H1 = B1 + 6;
+  const int b0base = t0 * B0 - 3, b1base = t1 * B1 - 3;
+  for (int e = threadIdx.x; e < H0 * H1; e += kBlock) {
+    const int h1 = e % H1, h0 = e / H1;
+    const int g0 = b0base + h0, g1 = b1base + h1;
+    const bool ok = g0 >= 0 && g0 < J && g1 >= 0 && g1 < J;
+    sin_[e] = ok ? c[int64_t(g0) * J + g1] : T(0);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < B0 * H1; e += kBlock) {
+    const int h1 = e % H1, b0 = e / H1;
+    const int j0 = t0 * B0 + b0;
+    if (j0 >= J) continue;
+    T m[7], g1c[7], g2c[7];
+    band_row(band, J, j0, m, g1c, g2c);
+    T a0 = T(0), a1 = T(0), a2 = T(0);
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+      const T v = sin_[(b0 + o) * H1 + h1];
+      a0 += m[o] * v;
+      a1 += g1c[o] * v;
+      a2 += g2c[o] * v;
+    }
+    s1[e] = a0;
+    s1[B0 * H1 + e] = a1;
+    s1[2 * B0 * H1 + e] = a2;
+  }
+  __syncthreads();
+  const T* band1 = band + size_t(3) * J * 7;
+  for (int e = threadIdx.x; e < B0 * B1; e += kBlock) {
+    const int b1 = e % B1, b0 = e / B1;
+    const int j0 = t0 * B0 + b0, j1 = t1 * B1 + b1;
+    if (j0 >= J || j1 >= J) continue;
+    T m[7], g1c[7], g2c[7];
+    band_row(band1, J, j1, m, g1c, g2c);
+    T a = T(0);
+#pragma unroll
+    for (int o = 0; o < 7; ++o) {
+      const int q = b0 * H1 + b1 + o;
+      a += m[o] * s1[2 * B0 * H1 + q] + g2c[o] * s1[q] + T(2) * g1c[o] * s1[B0 * H1 + q];
+    }
+    out[int64_t(j0) * J + j1] = lam * a;
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_lambda_diag(const double* band, int J, int64_t K,
                                                         double lam, double* out) {
@@ -1571,6 +1720,27 @@ hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(k_lambda_pass<T>, dim3(blocks_for(a.K)), dim3(kBlock), 0, st, a);
   return hipGetLastError();
 }
+template <typename T>
+hipError_t launch_lambda_fused(int D, const T* c, T* out, const T* band, int J, T lam, hipStream_t st) {
+  if (D == 3) {
+    const int nt1 = (J + kLamB1 - 1) / kLamB1, nt2 = (J + kLamB2 - 1) / kLamB2;
+    const int B1 = (J + nt1 - 1) / nt1, B2 = (J + nt2 - 1) / nt2;   // <= kLamB1, kLamB2
+    hipLaunchKernelGGL(k_lambda_fused3<T>, dim3(unsigned(J * nt1 * nt2)), dim3(kBlock), 0, st, c, out, band, J, B1,
+                       B2, nt1, nt2, lam);
+    return hipGetLastError();
+  }
+  if (D == 2) {
+    const int nt0 = (J + kLam2B0 - 1) / kLam2B0, nt1 = (J + kLam2B1 - 1) / kLam2B1;
+    const int B0 = (J + nt0 - 1) / nt0, B1 = (J + nt1 - 1) / nt1;
+    hipLaunchKernelGGL(k_lambda_fused2<T>, dim3(unsigned(nt0 * nt1)), dim3(kBlock), 0, st, c, out, band, J, B0, B1,
+                       nt1, lam);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+template hipError_t launch_lambda_fused<double>(int, const double*, double*, const double*, int, double, hipStream_t);
+template hipError_t launch_lambda_fused<float>(int, const float*, float*, const float*, int, float, hipStream_t);
+
 template hipError_t launch_lambda_pass<double>(const LambdaArgs<double>&, hipStream_t);
 template hipError_t launch_lambda_pass<float>(const LambdaArgs<float>&, hipStream_t);
 

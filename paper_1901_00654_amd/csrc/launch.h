@@ -45,6 +45,9 @@ hipError_t launch_worklist(int D, int pass, const DataArgs& a, int32_t* seg_coun
                            const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
                            hipStream_t st);
 template <typename T> hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipStream_t st);
+// out = lam * Lambda c in one kernel (d = 2 or 3); band: d blocks of [3][J][7].
+template <typename T>
+hipError_t launch_lambda_fused(int D, const T* c, T* out, const T* band, int J, T lam, hipStream_t st);
 hipError_t launch_lambda_diag(int D, const double* band, int J, int64_t K, double lam, double* out,
                               hipStream_t st);
 template <typename T> hipError_t launch_transfer(bool prolong, const TransferArgs<T>& a, hipStream_t st);

@@ -152,6 +152,10 @@ static void lambda_apply(Problem* P, int g, const T* c, T* out) {
   Level& L = P->lev[g];
   const int D = P->d;
   const int64_t K = L.K;
+  if (D == 2 || D == 3) {
+    hip_check(launch_lambda_fused<T>(D, c, out, lvl_band<T>(L), L.J, T(P->lam), P->stream), "lambda");
+    return;
+  }
   T* S = prob_lamS<T>(P);
   T* bufA = S;
   T* bufB = S + 3 * P->lev[P->G].K;

@@ -200,6 +200,50 @@ def serving(tsmg, workloads, R, slots, served_precision):
     return out
 
 
+def paper_experiments(tsmg, torch, workloads):
+    """The paper's Sec. 4 test (sigmoid data, n = 100,000, lambda = 0.2):
+    MGCG iterations and solve times for P = 2 under refinement G = 4..7
+    (Fig. 2) and for P = 1..4 at G = 5 (Table 2), and the condition number of
+    the V-cycle-preconditioned matrix B A at P = 2, G = 5 (Table 3), from the
+    V-cycle and the operator applied to the unit vectors."""
+    import numpy as np
+    out = {"lambda": 0.2, "tol": 1e-8, "refinement_P2": [], "dimensions_G5": []}
+
+    def run(P, N):
+        w = workloads.paper_sigmoid(P, N=N)
+        res = {"P": P, "G": int(np.log2(N))}
+        for name, prec in (("fp64", tsmg.TS_FP64), ("vcycle32", tsmg.TS_MIXED_FP32_VCYCLE)):
+            S = tsmg.Smoother(w["x"], w["y"], N, w["lam"], precision=prec, tol=1e-8, max_iter=20000)
+            try:
+                S.solve()
+                t0 = time.perf_counter()
+                _, status, info = S.solve()
+                res[name] = {"iterations": info["iterations"], "solve_s": time.perf_counter() - t0,
+                             "setup_s": info["setup_s"], "status": status}
+            finally:
+                S.close()
+        return res, w
+
+    for G in (4, 5, 6, 7):
+        out["refinement_P2"].append(run(2, 2 ** G)[0])
+    for P in (1, 2, 3, 4):
+        out["dimensions_G5"].append(run(P, 32)[0])
+    w = workloads.paper_sigmoid(2, N=32)
+    S = tsmg.Smoother(w["x"], w["y"], 32, w["lam"])
+    try:
+        K = S.K()
+        E = torch.eye(K, dtype=torch.float64)
+        A = np.column_stack([S.apply(S.G, E[:, k]).cpu().numpy() for k in range(K)])
+        B = np.column_stack([S.vcycle(E[:, k]).cpu().numpy() for k in range(K)])
+    finally:
+        S.close()
+    ev_a = np.linalg.eigvalsh(0.5 * (A + A.T))
+    ev_ba = np.sort(np.real(np.linalg.eigvals(B @ A)))
+    out["kappa_A_P2G5"] = float(ev_a[-1] / ev_a[0])
+    out["kappa_BA_P2G5"] = float(ev_ba[-1] / ev_ba[0])
+    return out
+
+
 def copy_calibration(torch):
     """A plain streaming kernel of known size (1 GiB read, 1 GiB written, as
     an elementwise multiply by one, which runs as a kernel where a same-type
@@ -255,6 +299,9 @@ def main():
                     help="mode of the served requests: FP32 CG with reliable updates, or FP64 CG "
                          "with an FP32 V-cycle")
     ap.add_argument("--only-serve", action="store_true", help="run only the serving leg")
+    ap.add_argument("--paper", action="store_true",
+                    help="only the paper's own test problem (Sec. 4): iterations under refinement and "
+                         "across dimensions, kappa(A) and kappa(BA); prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--only-apply", default=None, metavar="WORKLOAD",
@@ -273,6 +320,9 @@ def main():
     tsmg.load_library()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.paper:
+        print(json.dumps(paper_experiments(tsmg, torch, workloads)), flush=True)
+        return
     if args.only_serve:
         print(json.dumps(serving(tsmg, workloads, args.serve_requests, args.serve_slots,
                                  SERVE_PRECISION[args.serve_precision](tsmg))), flush=True)

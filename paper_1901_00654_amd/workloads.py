@@ -19,6 +19,8 @@ Workloads (all cubic, uniform knots on [0, 1]^d):
 - ``c4``  d=5, 16^5 (or 8^5) intervals, 16M scrambled Sobol points plus 4M
           points clustered in the corner at the origin,
           y = prod_k (1 + 0.5 cos(pi x_k)) + N(0, 0.1^2), lambda = 1e-3.
+- ``paper_sigmoid``  the test data of the paper's Sec. 4 (P = 1..4,
+          100,000 uniform points, sigmoid of ||x||^2 / P plus noise).
 - ``serving_trace``  a Poisson stream of requests with d in {2,3,4},
           intervals in {16,32,64} (at most 2e6 coefficients), 1e4..1e6
           uniform points, y = sin(2 pi sum_k x_k) + N(0, 0.1^2),
@@ -105,6 +107,20 @@ def c4(n=20_000_000, N=16, seed=4):
     y = np.prod(1.0 + 0.5 * np.cos(np.pi * x), axis=1)
     y = y + 0.1 * rng.standard_normal(n)
     return _pack("c4", x, y, N, 1e-3)
+
+
+def paper_sigmoid(P, n=100_000, N=32, lam=0.2, seed=11):
+    """The test data of Sec. 4: n uniform points in [0,1]^P and the
+    normalised multivariable sigmoid of ||x||^2 / P plus N(0, 0.1^2) noise.
+    The printed formula has a pole (a minus sign in the denominator); the
+    logistic form 1 / (1 + exp(-16 (||x||^2 / P - 0.5))), which maps into
+    [0, 1] as the paper states, is used. The paper gives no lambda; 0.2 is
+    where kappa(A) for P = 2, G = 5 meets its Table 3 value."""
+    rng = np.random.default_rng(seed)
+    x = rng.random((n, P))
+    f = 1.0 / (1.0 + np.exp(-16.0 * (np.sum(x * x, axis=1) / P - 0.5)))
+    y = f + 0.1 * rng.standard_normal(n)
+    return _pack("sigmoid%d" % P, x, y, N, lam)
 
 
 CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}

@@ -262,12 +262,12 @@ struct PointVals {
   T bm2[4];
 };
 
-template <int D, typename T, int NLEAD, int PPB>
-__device__ __forceinline__ void point_basis(const T (&s_tt)[D][PPB], int li, const T (&hc)[NLEAD > 0 ? NLEAD : 1][4],
+template <int D, typename T, int NLEAD>
+__device__ __forceinline__ void point_basis(const T* s_tt, int ppb, int li, const T (&hc)[NLEAD > 0 ? NLEAD : 1][4],
                                             PointVals<D, T>& q) {
   T tt[D];
 #pragma unroll
-  for (int p = 0; p < D; ++p) tt[p] = s_tt[p][li];
+  for (int p = 0; p < D; ++p) tt[p] = s_tt[p * ppb + li];
   q.w = T(1);
 #pragma unroll
   for (int k = 0; k < NLEAD; ++k) q.w *= ((hc[k][3] * tt[k] + hc[k][2]) * tt[k] + hc[k][1]) * tt[k] + hc[k][0];
@@ -311,11 +311,24 @@ __device__ __forceinline__ void point_scatter(const PointVals<D, T>& q, T s, T (
   }
 }
 
-// Byte offset of the FP64 patch accumulator in the dynamic LDS of the point
-// pass: after the staged coefficient patch (apply with staging), else 0.
-template <typename T, int MODE, bool STAGE_C>
-__host__ __device__ constexpr size_t lacc_offset(int patch) {
-  return (MODE == kApply && STAGE_C) ? ((size_t(patch) * sizeof(T) + 15) & ~size_t(15)) : 0;
+// Dynamic LDS of the point pass, in this order: the staged coefficient patch
+// (apply with staging), the FP64 patch accumulator, the staged point
+// positions [D][ppb], and the segment's items (work list: one packed word per
+// item; otherwise cell, first point and count tables).
+struct DataLds {
+  size_t lacc, tt, items, total;
+};
+__host__ __device__ constexpr size_t lds_round(size_t b) { return (b + 15) & ~size_t(15); }
+__host__ __device__ constexpr int max_items(int ppb, int Q) { return ppb / Q + 256; }
+
+template <int D, typename T, int MODE, bool STAGE_C, bool WL>
+__host__ __device__ constexpr DataLds data_lds(int patch, int ppb, int Q) {
+  DataLds l{};
+  l.lacc = (MODE == kApply && STAGE_C) ? lds_round(size_t(patch) * sizeof(T)) : 0;
+  l.tt = l.lacc + lds_round(size_t(patch) * sizeof(double));
+  l.items = l.tt + lds_round(size_t(D) * size_t(ppb) * sizeof(T));
+  l.total = l.items + size_t(max_items(ppb, Q)) * sizeof(int) * (WL ? 1 : 3);
+  return l;
 }
 
 // TBF >= 0: the tile side is 2^TBF (known at compile time, the usual case);
@@ -329,15 +342,9 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   constexpr int V = GP::V;
   constexpr int Q = GP::Q;
   constexpr int NLEAD = (D >= 3) ? D - 2 : 0;       // dimensions owned by the lane index
-  constexpr int PPB = GP::PPB;
-  constexpr int MAXI = GP::MAXI;
   constexpr bool STAGE_C = GP::STAGE_C;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int it_cell[MAXI];
-  __shared__ int it_lo[MAXI];
-  __shared__ int it_cnt[MAXI];
   __shared__ int scan_sh[kBlock / 64];
-  __shared__ T s_tt[D][PPB];   // level-g position of each point of the segment in its cell
 
   T* lc = reinterpret_cast<T*>(smem_raw);
   const int tbits = TBF >= 0 ? TBF : a.tb;
@@ -348,7 +355,14 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   for (int p = 0; p < D; ++p) patch *= P;
   // the patch accumulator is FP64 for both precisions: LDS float atomics are
   // several times slower than FP64 ones on gfx950
-  double* lacc = reinterpret_cast<double*>(smem_raw + lacc_offset<T, MODE, STAGE_C>(patch));
+  const DataLds lay = data_lds<D, T, MODE, STAGE_C, WL>(patch, a.ppb, Q);
+  double* lacc = reinterpret_cast<double*>(smem_raw + lay.lacc);
+  T* s_tt = reinterpret_cast<T*>(smem_raw + lay.tt);   // [D][ppb] level-g positions in the cell
+  const int maxi = max_items(a.ppb, Q);
+  uint32_t* s_items = reinterpret_cast<uint32_t*>(smem_raw + lay.items);
+  int* it_cell = reinterpret_cast<int*>(s_items);
+  int* it_lo = it_cell + maxi;
+  int* it_cnt = it_lo + maxi;
 
   int st[D];
   st[D - 1] = 1;
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
 #pragma unroll
       for (int p = 0; p < D; ++p) {
         const uint32_t cfp = (cf >> (a.G * (D - 1 - p))) & maskN;
-        s_tt[p][idx] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + i]) * scale;
+        s_tt[p * a.ppb + idx] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + i]) * scale;
       }
     }
     // ... and the coefficient patch; clear the accumulator
@@ -452,25 +466,28 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     }
     int n_items = 0;
     if constexpr (WL) {
-      n_items = item_e - item_b;
+      // the segment's items go to LDS with the points (at most ppb / Q +
+      // cells of a tile of them), so the item loop waits on no global load
+      n_items = min(item_e - item_b, maxi);
+      for (int e = threadIdx.x; e < n_items; e += kBlock) s_items[e] = a.wl_items[item_b + e];
       __syncthreads();
     } else {
       int n_items_all;
       const int first = block_exclusive_scan(nch, scan_sh, &n_items_all);
-      // first + k < PPB / Q + kMaxTileCells = MAXI (the host keeps ppb <= PPB)
-      for (int k = 0; k < nch && first + k < MAXI; ++k) {
+      // first + k < ppb / Q + kMaxTileCells = maxi
+      for (int k = 0; k < nch && first + k < maxi; ++k) {
         it_cell[first + k] = int(threadIdx.x);
         it_lo[first + k] = lo_rel + k * Q;
         it_cnt[first + k] = min(Q, cnt - k * Q);
       }
       __syncthreads();
-      n_items = min(n_items_all, MAXI);
+      n_items = min(n_items_all, maxi);
     }
 
     for (int it = grp; it < n_items; it += GP::NG) {
       int j, l0, l1;
       if constexpr (WL) {
-        const uint32_t w = a.wl_items[item_b + it];
+        const uint32_t w = s_items[it];
         j = int(w & 0xFFu);
         l0 = int((w >> kItemLoShift) & 0xFFFu);
         l1 = l0 + int(w >> kItemCntShift);
@@ -512,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       // DPP latencies better than two interleaved points at three waves
       for (int li = l0; li < l1; ++li) {
         PointVals<D, T> q0;
-        point_basis<D, T, NLEAD>(s_tt, li, hc, q0);
+        point_basis<D, T, NLEAD>(s_tt, a.ppb, li, hc, q0);
         T s0;
         if constexpr (MODE == kApply) s0 = group_sum<T, L>(q0.w * point_gather<D, T>(q0, cv));
         else if constexpr (MODE == kRhs) s0 = T(a.y[pos + li]);
@@ -1629,7 +1646,7 @@ static hipError_t launch_data_tb(const DataArgs& a, hipStream_t st) {
   const int Tg = 1 << a.tb;
   int patch = 1;
   for (int p = 0; p < D; ++p) patch *= (Tg + kDeg);
-  const size_t lds = lacc_offset<T, MODE, Group<D>::STAGE_C>(patch) + size_t(patch) * sizeof(double);
+  const size_t lds = data_lds<D, T, MODE, Group<D>::STAGE_C, WL>(patch, a.ppb, Group<D>::Q).total;
   if (a.ppb > Group<D>::PPB) return hipErrorInvalidValue;
   const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
   if (grid == 0) return hipSuccess;

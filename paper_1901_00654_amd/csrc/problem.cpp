@@ -778,8 +778,10 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     if (P->opt.points_per_block > 0) {
       P->ppb = std::max(64, std::min(ppb_max, P->opt.points_per_block));
     } else {
-      int64_t ppb = (n + 8191) / 8192;   // about 8192 workgroups
-      ppb = ((ppb + 63) / 64) * 64;
+      // the largest power of two <= n / 16384, within [256, ppb_max]
+      // (measured best on MI355X: 256 at 2e6 points, 512 at 1e7 and 2e7)
+      int64_t ppb = 256;
+      while (ppb * 2 <= n / 16384) ppb *= 2;
       P->ppb = int(std::max<int64_t>(std::min(256, ppb_max), std::min<int64_t>(ppb_max, ppb)));
     }
 

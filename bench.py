@@ -244,6 +244,48 @@ def paper_experiments(tsmg, torch, workloads):
     return out
 
 
+def solve_all(tsmg, torch, workloads, only=None, modes_only=None):
+    """Whole solves of every workload (c4 at 8^5 and 16^5 intervals) in the
+    three precision modes, to a relative FP64 true residual of 1e-8: time,
+    iterations, and the relative difference of each mixed solution to the
+    FP64 one."""
+    out = []
+    cases = [("c1", {}), ("c2", {}), ("c3", {}), ("c4", {"N": 8}), ("c4", {"N": 16})]
+    if only:
+        cases = [c for c in cases if "%s/%d" % (c[0], c[1].get("N", 0)) in only or c[0] in only]
+    modes = [("fp64", tsmg.TS_FP64), ("mixed", tsmg.TS_MIXED_FP32), ("vcycle32", tsmg.TS_MIXED_FP32_VCYCLE)]
+    if modes_only:
+        modes = [m for m in modes if m[0] in modes_only]
+    for name, kw in cases:
+        w = workloads.CONFIGS[name](**kw)
+        xd = torch.from_numpy(w["x"]).cuda()
+        yd = torch.from_numpy(w["y"]).cuda()
+        rec = {"workload": name, "d": w["d"], "N": w["N"], "n": len(w["y"])}
+        ref = None
+        for mname, prec in modes:
+            S = tsmg.Smoother(xd, yd, w["N"], w["lam"], lo=w["lo"], hi=w["hi"], precision=prec, tol=1e-8,
+                              max_iter=100000)
+            try:
+                t0 = time.perf_counter()
+                alpha, status, info = S.solve()
+                dt = time.perf_counter() - t0
+                r = {"status": status, "iterations": info["iterations"], "refinements": info["refinements"],
+                     "rel_residual": info["rel_residual"], "solve_s": dt, "setup_s": info["setup_s"]}
+                if ref is None:
+                    ref = alpha
+                else:
+                    r["rel_diff_vs_fp64"] = float(torch.linalg.norm(alpha - ref) / torch.linalg.norm(ref))
+                rec[mname] = r
+            finally:
+                S.close()
+            print(json.dumps({"progress": name, "N": w["N"], "mode": mname, **rec[mname]}), file=sys.stderr,
+                  flush=True)
+        out.append(rec)
+        del xd, yd, ref
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(torch):
     """A plain streaming kernel of known size (1 GiB read, 1 GiB written, as
     an elementwise multiply by one, which runs as a kernel where a same-type
@@ -292,13 +334,18 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the d=2..5 apply sweep")
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve-requests", type=int, default=16,
+    ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests of the serving trace to run (0: skip the serving leg)")
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent solves in the serving loop")
     ap.add_argument("--serve-precision", choices=["mixed", "vcycle32"], default="vcycle32",
                     help="mode of the served requests: FP32 CG with reliable updates, or FP64 CG "
                          "with an FP32 V-cycle")
     ap.add_argument("--only-serve", action="store_true", help="run only the serving leg")
+    ap.add_argument("--solve-all", action="store_true",
+                    help="only whole solves of c1..c4 in every precision mode; prints one JSON line")
+    ap.add_argument("--cases", default=None,
+                    help="with --solve-all: comma-separated workloads, e.g. c3 or c4/16")
+    ap.add_argument("--modes", default=None, help="with --solve-all: comma-separated modes (fp64,mixed,vcycle32)")
     ap.add_argument("--paper", action="store_true",
                     help="only the paper's own test problem (Sec. 4): iterations under refinement and "
                          "across dimensions, kappa(A) and kappa(BA); prints one JSON line")
@@ -320,6 +367,10 @@ def main():
     tsmg.load_library()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.solve_all:
+        print(json.dumps(solve_all(tsmg, torch, workloads, args.cases.split(",") if args.cases else None,
+                                   args.modes.split(",") if args.modes else None)), flush=True)
+        return
     if args.paper:
         print(json.dumps(paper_experiments(tsmg, torch, workloads)), flush=True)
         return

@@ -5,6 +5,8 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <utility>
 
 #include "problem.h"
@@ -43,6 +45,22 @@ void true_residual(Problem* P, const double* alpha, const double* b, double* r, 
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// TSMG_PROGRESS=k in the environment: every k-th iteration of a solve prints
+// its iteration count and recursive relative residual to stderr (for long
+// solves run under a watchdog that expects output).
+int progress_every() {
+  const char* e = std::getenv("TSMG_PROGRESS");
+  const int k = e ? std::atoi(e) : 0;
+  return k > 0 ? k : 0;
+}
+
+void report(int every, const char* mode, int it, double rel) {
+  if (every > 0 && it % every == 0) {
+    std::fprintf(stderr, "tsmg %s iteration %d rel. residual %.3e\n", mode, it, rel);
+    std::fflush(stderr);
+  }
+}
 
 }  // namespace
 
@@ -90,6 +108,7 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
     hip_check(launch_scale_copy<double, double>(b, r, K, 1.0, nullptr, st), "copy");
   }
   const double tol = P->opt.tol;
+  const int every = progress_every();
   int total = 0, restarts = 0;
   double rel_true = 1.0;
   for (;;) {
@@ -108,6 +127,7 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
       ++total;
       if (!finite_pos(h[0]) || !std::isfinite(h[1]))
         throw Error{TS_EBREAKDOWN, "CG breakdown: p'Ap = " + std::to_string(h[0])};
+      report(every, pc32 ? "vcycle32" : "fp64", total, std::sqrt(h[1]) / bnorm);
       if (std::sqrt(h[1]) / bnorm <= tol) break;
       if (pc32) dot_op<double, double>(P, r, z, K, kRZo);   // r_new' z_old
       precondition(P, pc32, r, z, kRR);
@@ -163,6 +183,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
   const double bnorm = std::sqrt(bb);
   const double tol = P->opt.tol;
   const double delta = (P->opt.inner_tol > 0.0 && P->opt.inner_tol < 1.0) ? P->opt.inner_tol : 0.1;
+  const int every = progress_every();
   if (use_start) {
     true_residual(P, alpha, b, r, v);
   } else {
@@ -194,6 +215,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
       ++total;
       if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
         throw Error{TS_EBREAKDOWN, "mixed CG breakdown: non-finite scalar"};
+      report(every, "mixed", total, std::sqrt(h[1]));
       const bool breakdown = !(h[0] > 0.0);   // the device skipped the step
       if (breakdown && fresh) hip_check(launch_scale_copy<float, float>(p, dl, K, 1.0, nullptr, st), "copy");
       const double rn = std::sqrt(h[1]);

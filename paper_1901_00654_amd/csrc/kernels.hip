@@ -1,16 +1,24 @@
 // Device kernels of tsmg for gfx950 (CDNA4, wave64).
 //
 // Hot path (per operator apply A_g c, Sec. 2.4 / Alg. 2-4 of arXiv:1901.00654):
-//   k_lambda_pass  out  = lambda Lambda_g c, one banded pass per dimension
+//   k_lambda_fused2/3, k_lambda_pass
+//                  out  = lambda Lambda_g c (one LDS-tiled kernel for d = 2, 3,
+//                  one banded pass per dimension otherwise)
 //   k_data<kApply> out += Phi_g'(Phi_g c), points sorted by knot cell,
+//                  segments and items from a precomputed work list,
 //                  coefficient patch of a cell tile staged in LDS, per-point
 //                  tensor basis as products of 1D cubic values in registers,
 //                  scatter reduced in LDS before one atomic per patch entry.
-// V-cycle pieces: Jacobi epilogues (Alg. 6), subdivision prolongation and
-// restriction passes (Sec. 3.2.3), coarse GEMV with the precomputed inverse
-// (Sec. 3.2.4); CG vector kernels with device-resident scalars (Alg. 8).
-// Setup: binning, offsets, Jacobi diagonal (Alg. 5 + Kronecker diagonal),
-// coarse assembly by polynomial moments, Gauss-Jordan inversion.
+//   k_stencil_apply(_small)
+//                  out = A_g x on levels assembled as 7^d-point stencils,
+//                  with Jacobi / residual epilogues.
+// V-cycle pieces: Jacobi kernels (Alg. 6), subdivision prolongation and
+// restriction, pass by pass or fused (Sec. 3.2.3), coarse GEMV with the
+// precomputed inverse (Sec. 3.2.4); CG vector kernels with device-resident
+// scalars (Alg. 8).
+// Setup: binning, offsets, work lists, Jacobi diagonal (Alg. 5 + Kronecker
+// diagonal), stencil assembly from per-cell polynomial moments, Gauss-Jordan
+// inversion of A_1.
 #include <algorithm>
 
 #include "common.h"
@@ -32,15 +40,6 @@ __device__ __forceinline__ void cubic_basis(T t, T (&b)[4]) {
   b[1] = two3 - t2 + half * t3;
   b[2] = two3 - s2 + half * s3;
   b[3] = t3 * sixth;
-}
-
-template <typename T>
-__device__ __forceinline__ T sel4(const T (&b)[4], int a) {
-  T r = b[0];
-  r = (a == 1) ? b[1] : r;
-  r = (a == 2) ? b[2] : r;
-  r = (a == 3) ? b[3] : r;
-  return r;
 }
 
 // Morton (bit-interleaved) index -> per-dimension coordinates, `bits` bits
@@ -68,10 +67,9 @@ __device__ __forceinline__ int xcd_block() {
 }
 
 // ---------------------------------------------------------------------------
-// Unrolled tensor-product gather / scatter over the innermost dimensions
-// p..D-1 of a patch with strides st[] (last stride 1). Gather is sum-factorised
-// (innermost 4-term rows first); scatter multiplies the weight down the same
-// tree and adds into LDS with hardware atomics.
+// Unrolled, sum-factorised tensor-product gather over the innermost
+// dimensions p..D-1 of a patch with strides st[] (last stride 1), innermost
+// 4-term rows first (used by the evaluation of a fit).
 template <int D, int p, typename T>
 struct Inner {
   static __device__ __forceinline__ T gather(const T* lc, int o, const T (&B)[D][4],
@@ -81,28 +79,11 @@ struct Inner {
     for (int a = 0; a < 4; ++a) r += B[p][a] * Inner<D, p + 1, T>::gather(lc, o + a * st[p], B, st);
     return r;
   }
-  static __device__ __forceinline__ void scatter(T* acc, int o, const T (&B)[D][4],
-                                                 const int (&st)[D], T w) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a) Inner<D, p + 1, T>::scatter(acc, o + a * st[p], B, st, w * B[p][a]);
-  }
-  static __device__ __forceinline__ void scatter_sq(T* acc, int o, const T (&B)[D][4],
-                                                    const int (&st)[D], T w) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-      Inner<D, p + 1, T>::scatter_sq(acc, o + a * st[p], B, st, w * B[p][a] * B[p][a]);
-  }
 };
 template <int D, typename T>
 struct Inner<D, D, T> {
   static __device__ __forceinline__ T gather(const T* lc, int o, const T (&)[D][4], const int (&)[D]) {
     return lc[o];
-  }
-  static __device__ __forceinline__ void scatter(T* acc, int o, const T (&)[D][4], const int (&)[D], T w) {
-    atomicAdd(&acc[o], w);
-  }
-  static __device__ __forceinline__ void scatter_sq(T* acc, int o, const T (&)[D][4], const int (&)[D], T w) {
-    atomicAdd(&acc[o], w);
   }
 };
 
@@ -133,25 +114,6 @@ __device__ __forceinline__ T patch_gather(const T* lc, int base, const T (&B)[D]
   }
 }
 
-template <int D, typename T, bool SQ>
-__device__ __forceinline__ void patch_scatter(T* acc, int base, const T (&B)[D][4], const int (&st)[D], T w0) {
-  if constexpr (Split<D>::L == 0) {
-    if constexpr (SQ) Inner<D, 0, T>::scatter_sq(acc, base, B, st, w0);
-    else Inner<D, 0, T>::scatter(acc, base, B, st, w0);
-  } else {
-    T r0 = B[0][0], r1 = B[0][1], r2 = B[0][2], r3 = B[0][3];
-    int o = base;
-#pragma unroll 1
-    for (int a = 0; a < 4; ++a) {
-      const T w = SQ ? w0 * r0 * r0 : w0 * r0;
-      if constexpr (SQ) Inner<D, 1, T>::scatter_sq(acc, o, B, st, w);
-      else Inner<D, 1, T>::scatter(acc, o, B, st, w);
-      r0 = r1; r1 = r2; r2 = r3;
-      o += st[0];
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // The data term of one level: out += Phi_g'(Phi_g c) (kApply), Phi_g'y (kRhs)
 // or diag(Phi_g'Phi_g) (kDiag).
@@ -160,7 +122,8 @@ __device__ __forceinline__ void patch_scatter(T* acc, int base, const T (&B)[D][
 // are in Morton order of their finest cell, so each Morton-aligned tile of
 // 2^tb level-g cells per dimension is one contiguous point range. Per tile
 // segment the workgroup stages the (2^tb + 3)^D coefficient patch in LDS and
-// cuts the segment into items: runs of at most Q points of one cell.
+// cuts the segment into items: runs of at most Q points of one cell (read
+// from the level's work list, or derived from the cell offsets on the fly).
 //
 // Items go to lane groups of L = 4^(D-2) lanes (one lane for D <= 2). A
 // lane holds 16 coefficients of the cell's 4^D patch in registers - the last

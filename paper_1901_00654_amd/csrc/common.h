@@ -36,12 +36,23 @@ struct DataArgs {
   int g;                    // this level
   int tb;                   // tile side 2^tb level-g cells per dimension (tb <= g)
   int ppb;                  // points per workgroup (<= kMaxPointsPerBlock[d])
-  // Optional work list of this level (built once at setup; null: the kernel
-  // derives the same segments and items from mkey and off on the fly):
-  const int32_t* wl_first;  // [workgroups + 1] first segment of each workgroup
-  const int4* wl_segs;      // [segments + 1] {first point, end point, tile, first item}
-  const uint32_t* wl_items; // [items] cell in tile | first point - segment start << 8 | count << 20
+  // Optional work list of this level, built once at setup (null: each
+  // workgroup takes ppb points and derives its tile segments and items from
+  // mkey and off on the fly). With a work list a workgroup takes whole tile
+  // segments - up to several chunks of at most ppb points each - staging the
+  // coefficient patch and flushing the accumulator once per segment.
+  const int32_t* wl_first;  // [workgroups + 1] first chunk of each workgroup
+  const int4* wl_chunks;    // [chunks + 1] {first point, end point, first item,
+                            //  tile | kChunkFirst | kChunkLast (of its segment)}
+  const uint32_t* wl_items; // [items] cell in tile | first point - chunk start << 8 | count << 20
+  int wl_groups;            // workgroups of the work list
 };
+constexpr uint32_t kChunkFirst = 1u << 31;   // first chunk of a tile segment
+constexpr uint32_t kChunkLast = 1u << 30;    // last chunk of a tile segment
+constexpr uint32_t kChunkTile = kChunkLast - 1u;
+
+// Points per item (a cell's run of points given to one lane group), by d.
+constexpr int kItemQ[kMaxDim + 1] = {0, 16, 16, 8, 16, 32};
 
 // Packing of one work-list item (a cell's run of at most Q points).
 constexpr int kItemLoShift = 8;

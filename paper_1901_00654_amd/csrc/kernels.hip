@@ -165,7 +165,7 @@ template <int D>
 struct Group {
   static constexpr int L = (D <= 2) ? 1 : (1 << (2 * (D - 2)));   // lanes per item
   static constexpr int V = (D == 1) ? 4 : 16;                      // coefficients per lane
-  static constexpr int Q = (D <= 2) ? 16 : (D == 3 ? 8 : (D == 4 ? 16 : 32));   // points per item
+  static constexpr int Q = kItemQ[D];                              // points per item
   static constexpr int NG = kBlock / L;                            // groups per workgroup
   static constexpr int PPB = kMaxPointsPerBlock[D];                // points per workgroup, at most
   static constexpr int MAXI = PPB / Q + kMaxTileCells;             // items per tile segment, at most
@@ -356,38 +356,43 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   }
 
   const int wg = xcd_block();
-  int64_t pos = 0, end = 0;
-  int s_cur = 0, s_end = 0;
+  int64_t pos = 0, end = 0, seg_end = 0;
+  int c_cur = 0, c_end = 0;
   if constexpr (WL) {
-    s_cur = a.wl_first[wg];
-    s_end = a.wl_first[wg + 1];
+    c_cur = a.wl_first[wg];
+    c_end = a.wl_first[wg + 1];
   } else {
     pos = int64_t(wg) * a.ppb;
     end = min(a.n, pos + int64_t(a.ppb));
   }
+  int org[D];
+  // With a work list the loop runs over the workgroup's chunks; the first
+  // chunk of a tile segment stages the coefficient patch and clears the
+  // accumulator, the last one flushes it. Without, over the tile segments of
+  // the workgroup's ppb points, each one chunk.
   for (;;) {
+    bool seg_first = true, seg_last = true;
     uint32_t tile;
-    int64_t seg_end;
     int item_b = 0, item_e = 0;
     if constexpr (WL) {
-      if (s_cur >= s_end) break;
-      const int4 sd = a.wl_segs[s_cur];
-      pos = sd.x;
-      seg_end = sd.y;
-      tile = uint32_t(sd.z);
-      item_b = sd.w;
-      item_e = a.wl_segs[s_cur + 1].w;
-      ++s_cur;
+      if (c_cur >= c_end) break;
+      const int4 cd = a.wl_chunks[c_cur];
+      pos = cd.x;
+      seg_end = cd.y;
+      item_b = cd.z;
+      item_e = a.wl_chunks[c_cur + 1].z;
+      const uint32_t tw = uint32_t(cd.w);
+      tile = tw & kChunkTile;
+      seg_first = (tw & kChunkFirst) != 0;
+      seg_last = (tw & kChunkLast) != 0;
+      ++c_cur;
     } else {
       if (pos >= end) break;
       tile = a.mkey[pos] >> S;
       seg_end = min(end, int64_t(a.off[size_t(tile + 1) << S]));
       if (seg_end <= pos) break;   // offsets are monotone with off[N^D] = n; never taken
     }
-    int org[D];
-    morton_decode<D>(tile, a.g - tbits, org);
-#pragma unroll
-    for (int p = 0; p < D; ++p) org[p] *= Tg;
+    if (!seg_first) __syncthreads();   // the previous chunk's points and items are consumed
 
     // per-cell point ranges of this segment, cut into items of <= Q points;
     // thread j owns cell j of the tile (cells_in_tile <= kBlock)
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       lo_rel = int(lo - pos);
       nch = (cnt + Q - 1) / Q;
     }
-    // stage the segment's points (one coalesced pass) ...
+    // stage the chunk's points (one coalesced pass)
     const int mseg = int(seg_end - pos);
     for (int idx = threadIdx.x; idx < mseg; idx += kBlock) {
       const size_t i = size_t(pos) + size_t(idx);
@@ -412,24 +417,29 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
         s_tt[p * a.ppb + idx] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + i]) * scale;
       }
     }
-    // ... and the coefficient patch; clear the accumulator
-    for (int e = threadIdx.x; e < patch; e += kBlock) {
-      if constexpr (MODE == kApply && STAGE_C) {
-        int rem = e;
-        int64_t gidx = 0;
+    if (seg_first) {
+      morton_decode<D>(tile, a.g - tbits, org);
 #pragma unroll
-        for (int p = 0; p < D; ++p) {
-          const int l = rem / st[p];
-          rem -= l * st[p];
-          gidx = gidx * Jg + (org[p] + l);
+      for (int p = 0; p < D; ++p) org[p] *= Tg;
+      // the coefficient patch (once per segment); clear the accumulator
+      for (int e = threadIdx.x; e < patch; e += kBlock) {
+        if constexpr (MODE == kApply && STAGE_C) {
+          int rem = e;
+          int64_t gidx = 0;
+#pragma unroll
+          for (int p = 0; p < D; ++p) {
+            const int l = rem / st[p];
+            rem -= l * st[p];
+            gidx = gidx * Jg + (org[p] + l);
+          }
+          lc[e] = cin[gidx];
         }
-        lc[e] = cin[gidx];
+        lacc[e] = 0.0;
       }
-      lacc[e] = 0.0;
     }
     int n_items = 0;
     if constexpr (WL) {
-      // the segment's items go to LDS with the points (at most ppb / Q +
+      // the chunk's items go to LDS with the points (at most ppb / Q +
       // cells of a tile of them), so the item loop waits on no global load
       n_items = min(item_e - item_b, maxi);
       for (int e = threadIdx.x; e < n_items; e += kBlock) s_items[e] = a.wl_items[item_b + e];
@@ -505,6 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
         atomicAdd(&lacc[base + off], double(acc[v]));
       }
     }
+    if (!seg_last) continue;
     __syncthreads();
 
     for (int e = threadIdx.x; e < patch; e += kBlock) {
@@ -526,62 +537,6 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   }
 }
 
-// Work list of the point pass of one level (setup): the same tile segments
-// and items the pass derives on the fly, per logical workgroup. PASS 0 counts
-// segments and items per workgroup; PASS 1 writes them at the offsets given
-// by the exclusive scans seg_base / item_base of those counts.
-template <int D, int TBF, int PASS>
-__global__ __launch_bounds__(kBlock) void k_worklist(DataArgs a, int32_t* seg_count, int32_t* item_count,
-                                                     const int32_t* seg_base, const int32_t* item_base,
-                                                     int4* segs, uint32_t* items) {
-  constexpr int Q = Group<D>::Q;
-  __shared__ int scan_sh[kBlock / 64];
-  const int tbits = TBF >= 0 ? TBF : a.tb;
-  const int sh = a.G - a.g;
-  const int S = D * (sh + tbits);
-  const int cells_in_tile = 1 << (D * tbits);
-  const int wg = blockIdx.x;
-  int64_t pos = int64_t(wg) * a.ppb;
-  const int64_t end = min(a.n, pos + int64_t(a.ppb));
-  int nseg = 0, nitem = 0;
-  int sb = 0, ib = 0;
-  if constexpr (PASS == 1) {
-    sb = seg_base[wg];
-    ib = item_base[wg];
-  }
-  while (pos < end) {
-    const uint32_t tile = a.mkey[pos] >> S;
-    const int64_t seg_end = min(end, int64_t(a.off[size_t(tile + 1) << S]));
-    if (seg_end <= pos) break;
-    int nch = 0, cnt = 0, lo_rel = 0;
-    if (int(threadIdx.x) < cells_in_tile) {
-      const size_t gc = (size_t(tile) << (D * tbits)) + size_t(threadIdx.x);
-      int64_t lo = a.off[gc << (D * sh)], hi = a.off[(gc + 1) << (D * sh)];
-      lo = max(lo, pos);
-      hi = min(hi, seg_end);
-      cnt = hi > lo ? int(hi - lo) : 0;
-      lo_rel = int(lo - pos);
-      nch = (cnt + Q - 1) / Q;
-    }
-    int total;
-    const int first = block_exclusive_scan(nch, scan_sh, &total);
-    if constexpr (PASS == 1) {
-      for (int k = 0; k < nch; ++k)
-        items[ib + nitem + first + k] = uint32_t(threadIdx.x) | (uint32_t(lo_rel + k * Q) << kItemLoShift) |
-                                        (uint32_t(min(Q, cnt - k * Q)) << kItemCntShift);
-      if (threadIdx.x == 0) segs[sb + nseg] = make_int4(int(pos), int(seg_end), int(tile), ib + nitem);
-    }
-    ++nseg;
-    nitem += total;
-    pos = seg_end;
-  }
-  if constexpr (PASS == 0) {
-    if (threadIdx.x == 0) {
-      seg_count[wg] = nseg;
-      item_count[wg] = nitem;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // lambda * Lambda_g c by the three-accumulator sum factorisation of
@@ -1611,7 +1566,7 @@ static hipError_t launch_data_tb(const DataArgs& a, hipStream_t st) {
   for (int p = 0; p < D; ++p) patch *= (Tg + kDeg);
   const size_t lds = data_lds<D, T, MODE, Group<D>::STAGE_C, WL>(patch, a.ppb, Group<D>::Q).total;
   if (a.ppb > Group<D>::PPB) return hipErrorInvalidValue;
-  const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
+  const unsigned grid = WL ? unsigned(a.wl_groups) : unsigned((a.n + a.ppb - 1) / a.ppb);
   if (grid == 0) return hipSuccess;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE, TBF, WL>),
@@ -1634,42 +1589,6 @@ static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
   return launch_data_tb<D, T, MODE, -1, false>(a, st);
 }
 
-template <int D, int TBF>
-static hipError_t launch_worklist_tb(int pass, const DataArgs& a, int32_t* seg_count, int32_t* item_count,
-                                     const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
-                                     hipStream_t st) {
-  const unsigned grid = unsigned((a.n + a.ppb - 1) / a.ppb);
-  if (grid == 0) return hipSuccess;
-  if (pass == 0)
-    hipLaunchKernelGGL((k_worklist<D, TBF, 0>), dim3(grid), dim3(kBlock), 0, st, a, seg_count, item_count, seg_base,
-                       item_base, segs, items);
-  else
-    hipLaunchKernelGGL((k_worklist<D, TBF, 1>), dim3(grid), dim3(kBlock), 0, st, a, seg_count, item_count, seg_base,
-                       item_base, segs, items);
-  return hipGetLastError();
-}
-
-template <int D>
-static hipError_t launch_worklist_d(int pass, const DataArgs& a, int32_t* seg_count, int32_t* item_count,
-                                    const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
-                                    hipStream_t st) {
-  if (a.tb == kTileBits[D])
-    return launch_worklist_tb<D, kTileBits[D]>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
-  return launch_worklist_tb<D, -1>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
-}
-
-hipError_t launch_worklist(int D, int pass, const DataArgs& a, int32_t* seg_count, int32_t* item_count,
-                           const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
-                           hipStream_t st) {
-  switch (D) {
-    case 1: return launch_worklist_d<1>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
-    case 2: return launch_worklist_d<2>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
-    case 3: return launch_worklist_d<3>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
-    case 4: return launch_worklist_d<4>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
-    case 5: return launch_worklist_d<5>(pass, a, seg_count, item_count, seg_base, item_base, segs, items, st);
-  }
-  return hipErrorInvalidValue;
-}
 
 template <typename T, int MODE>
 static hipError_t launch_data_t(int D, const DataArgs& a, hipStream_t st) {

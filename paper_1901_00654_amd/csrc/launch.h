@@ -38,12 +38,7 @@ struct TransferArgs {
 };
 
 hipError_t launch_data(int D, bool fp32, int mode, const DataArgs& a, hipStream_t st);
-// Work list of the point pass (a.wl_* unused): pass 0 writes per-workgroup
-// segment and item counts, pass 1 the segments (plus nothing for the
-// sentinel, which the host writes) and items at the scanned offsets.
-hipError_t launch_worklist(int D, int pass, const DataArgs& a, int32_t* seg_count, int32_t* item_count,
-                           const int32_t* seg_base, const int32_t* item_base, int4* segs, uint32_t* items,
-                           hipStream_t st);
+
 template <typename T> hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipStream_t st);
 // out = lam * Lambda c in one kernel (d = 2 or 3); band: d blocks of [3][J][7].
 template <typename T>

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -196,49 +197,90 @@ static DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out
   a.ppb = P->ppb;
   if (L.wl_items.p) {
     a.wl_first = L.wl_first.p;
-    a.wl_segs = L.wl_segs.p;
+    a.wl_chunks = L.wl_chunks.p;
     a.wl_items = L.wl_items.p;
+    a.wl_groups = L.wl_groups;
   }
   return a;
 }
 
-// Work list of the point pass on level g: segments and items per workgroup,
-// counted, scanned on the host and written on the device.
-static void build_worklist(Problem* P, int g) {
+// Work list of the point pass on level g, from the finest cell offsets
+// (host copy `off`). The nonempty tiles, in Morton order, are cut into
+// segments, segments into chunks of at most ppb points, chunks into items (a
+// cell's run of at most Q points inside the chunk). Two ways of dealing
+// segments to workgroups, chosen by what measured faster on MI355X:
+// - split (d <= 3, small coefficient patches): workgroup w takes exactly the
+//   points [w ppb, (w+1) ppb), so a tile that straddles a boundary becomes a
+//   segment in each of the two workgroups;
+// - packed (d >= 4, where staging and flushing a (2^tb+3)^d patch twice
+//   costs more): whole tiles, cut only when longer than ppb, are packed into
+//   workgroups of at most ppb points.
+static void build_worklist(Problem* P, int g, const std::vector<int32_t>& off) {
+  const bool split = P->d <= 3;
   Level& L = P->lev[g];
-  hipStream_t st = P->stream;
-  DataArgs a = data_args(P, g, false, nullptr, nullptr);
-  a.wl_first = nullptr;
-  a.wl_segs = nullptr;
-  a.wl_items = nullptr;
-  const int64_t nwg = (P->n + P->ppb - 1) / P->ppb;
-  DevBuf<int32_t> cnt, ibase;
-  cnt.alloc(size_t(2 * nwg));
-  hip_check(launch_worklist(P->d, 0, a, cnt.p, cnt.p + nwg, nullptr, nullptr, nullptr, nullptr, st), "worklist");
-  std::vector<int32_t> h(static_cast<size_t>(2 * nwg));
-  hip_check(hipMemcpyAsync(h.data(), cnt.p, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st), "download");
-  hip_check(hipStreamSynchronize(st), "sync");
-  std::vector<int32_t> first(static_cast<size_t>(nwg + 1)), ib(static_cast<size_t>(nwg));
-  int64_t nseg = 0, nitem = 0;
-  for (int64_t w = 0; w < nwg; ++w) {
-    first[size_t(w)] = int32_t(nseg);
-    ib[size_t(w)] = int32_t(nitem);
-    nseg += h[size_t(w)];
-    nitem += h[size_t(nwg + w)];
-    if (nseg >= INT32_MAX || nitem >= INT32_MAX) throw Error{TS_EINVAL, "work list exceeds 2^31 entries"};
+  const int D = P->d;
+  const int sh = P->G - g;
+  const int tb = L.tb;
+  const int Q = kItemQ[D];
+  const int64_t ch = P->ppb;
+  const int cells_in_tile = 1 << (D * tb);
+  const int64_t ntiles = int64_t(1) << (D * (g - tb));
+  auto cell_start = [&](int64_t c) { return int64_t(off[size_t(c << (D * sh))]); };   // level-g Morton cell c
+  std::vector<int32_t> first;
+  std::vector<int4> chunks;
+  std::vector<uint32_t> items;
+  int64_t wg_points = 0;
+  for (int64_t t = 0; t < ntiles; ++t) {
+    const int64_t c0 = t << (D * tb);
+    const int64_t a = cell_start(c0), b = cell_start(c0 + cells_in_tile);
+    if (a == b) continue;
+    int j = 0;   // the first cell of the tile that still holds points at or after k0
+    for (int64_t s0 = a, s1; s0 < b; s0 = s1) {
+      // one segment [s0, s1) of the tile
+      if (split) {
+        s1 = std::min(b, (s0 / ch + 1) * ch);
+        if (s0 % ch == 0) first.push_back(int32_t(chunks.size()));
+      } else {
+        s1 = std::min(b, s0 + ch);
+        if (first.empty() || wg_points + (s1 - s0) > ch) {
+          first.push_back(int32_t(chunks.size()));
+          wg_points = 0;
+        }
+        wg_points += s1 - s0;
+      }
+      for (int64_t k0 = s0; k0 < s1; k0 += ch) {
+        const int64_t k1 = std::min(s1, k0 + ch);
+        uint32_t flags = uint32_t(t);
+        if (k0 == s0) flags |= kChunkFirst;
+        if (k1 == s1) flags |= kChunkLast;
+        chunks.push_back(make_int4(int(k0), int(k1), int(items.size()), int(flags)));
+        while (j < cells_in_tile && cell_start(c0 + j + 1) <= k0) ++j;
+        for (int jj = j; jj < cells_in_tile; ++jj) {
+          if (cell_start(c0 + jj) >= k1) break;
+          const int64_t lo = std::max(cell_start(c0 + jj), k0), hi = std::min(cell_start(c0 + jj + 1), k1);
+          for (int64_t q = lo; q < hi; q += Q)
+            items.push_back(uint32_t(jj) | (uint32_t(q - k0) << kItemLoShift) |
+                            (uint32_t(std::min<int64_t>(Q, hi - q)) << kItemCntShift));
+        }
+      }
+    }
+    if (int64_t(items.size()) >= INT32_MAX || int64_t(chunks.size()) >= INT32_MAX)
+      throw Error{TS_EINVAL, "work list exceeds 2^31 entries"};
   }
-  first[size_t(nwg)] = int32_t(nseg);
+  first.push_back(int32_t(chunks.size()));
+  chunks.push_back(make_int4(0, 0, int(items.size()), 0));
+  if (items.empty()) items.push_back(0u);
+  hipStream_t st = P->stream;
+  L.wl_groups = int(first.size()) - 1;
   L.wl_first.alloc(first.size());
-  ibase.alloc(ib.size());
-  L.wl_segs.alloc(size_t(nseg + 1));
-  L.wl_items.alloc(size_t(std::max<int64_t>(nitem, 1)));
-  const int4 sentinel = make_int4(0, 0, 0, int(nitem));
+  L.wl_chunks.alloc(chunks.size());
+  L.wl_items.alloc(items.size());
   hip_check(hipMemcpyAsync(L.wl_first.p, first.data(), first.size() * sizeof(int32_t), hipMemcpyHostToDevice, st),
             "upload");
-  hip_check(hipMemcpyAsync(ibase.p, ib.data(), ib.size() * sizeof(int32_t), hipMemcpyHostToDevice, st), "upload");
-  hip_check(hipMemcpyAsync(L.wl_segs.p + nseg, &sentinel, sizeof(int4), hipMemcpyHostToDevice, st), "upload");
-  hip_check(launch_worklist(P->d, 1, a, nullptr, nullptr, L.wl_first.p, ibase.p, L.wl_segs.p, L.wl_items.p, st),
-            "worklist");
+  hip_check(hipMemcpyAsync(L.wl_chunks.p, chunks.data(), chunks.size() * sizeof(int4), hipMemcpyHostToDevice, st),
+            "upload");
+  hip_check(hipMemcpyAsync(L.wl_items.p, items.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st),
+            "upload");
   hip_check(hipStreamSynchronize(st), "sync");   // host vectors go out of scope
 }
 
@@ -611,12 +653,12 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
     const int64_t K = ipow(J, d);
     levels += 56 * K + int64_t(d) * 3 * J * 7 * 12;
     const bool st = want_stencil(d, J, n, opt.stencil_mode, stencil_budget_for(stencil_budget));
-    if (!st) {   // work list: items <= n, segments <= workgroups + nonempty tiles
-      const int64_t nwg = (n + 255) / 256 + 1;
+    if (!st) {   // work list: items <= n; workgroups <= chunks <= nonempty tiles
+                 // + n / 64 (ppb >= 64)
       const int tb = std::min(kTileBits[d], g);
       const int64_t ntiles = int64_t(1) << (d * (g - tb));
-      levels += 8 * (nwg + 1) + 16 * (nwg + std::min(n, ntiles) + 1) + 4 * n;
-      stencil_tmp = std::max(stencil_tmp, 8 * nwg);
+      const int64_t chunks = std::min(n, ntiles) + n / 64 + 2;
+      levels += 20 * chunks + 4 * n + 4;
     }
     // level 1 always carries its stencil: A_1 is expanded from it
     if (g == 1 || st) {
@@ -841,8 +883,19 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     }
 
     // --- work lists of the point pass on the matrix-free levels
-    for (int g = 1; g <= G; ++g)
-      if (!P->lev[g].stencil) build_worklist(P, g);
+    {
+      std::vector<int32_t> off_h;
+      for (int g = 1; g <= G; ++g) {
+        if (P->lev[g].stencil) continue;
+        if (off_h.empty()) {
+          off_h.resize(size_t((int64_t(1) << (G * d)) + 1));
+          hip_check(hipMemcpyAsync(off_h.data(), P->off.p, off_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                    "download");
+          hip_check(hipStreamSynchronize(st), "sync");
+        }
+        build_worklist(P, g, off_h);
+      }
+    }
 
     // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)
     for (int g = 1; g <= G; ++g) compute_diag(P, g);

@@ -88,8 +88,9 @@ struct Level {
   DevBuf<int32_t> soffs;           // [7^d] flat index offset of each stencil point
   // work list of the point pass (levels applied matrix-free)
   DevBuf<int32_t> wl_first;        // [workgroups + 1]
-  DevBuf<int4> wl_segs;            // [segments + 1]
+  DevBuf<int4> wl_chunks;          // [chunks + 1]
   DevBuf<uint32_t> wl_items;       // [items]
+  int wl_groups = 0;
 };
 
 constexpr int kSlots = 16;

@@ -583,16 +583,26 @@ __global__ __launch_bounds__(kBlock) void k_lambda_pass(LambdaArgs<T> a) {
   }
 }
 
-// lambda * diag(Lambda_g) from the diagonals of the 1D factors; `band` holds
-// [D][3][J][7] (each dimension has its own mesh width).
-// lambda * Lambda c in one kernel for d = 2 and 3: each workgroup computes
-// a tile of the output from a halo-extended tile of c staged in LDS, running
-// the three-accumulator recursion of k_lambda_pass over the dimensions in
-// LDS (out-of-grid halo entries are zero, which drops the same taps the pass
-// form skips). band: d blocks of [3][J][7] (M, G1, G2 per dimension).
-constexpr int kLamB1 = 8;    // d = 3: output rows per tile along dimension 1 (dimension 0: 1 row)
-constexpr int kLamB2 = 32;   // last dimension
-constexpr int kLamH1 = kLamB1 + 6, kLamH2 = kLamB2 + 6;
+// lambda * Lambda c in one kernel for d = 2 and 3, running the
+// three-accumulator recursion of k_lambda_pass over the dimensions on chip
+// (out-of-grid entries of c are zero, which drops the same taps the pass form
+// skips). band: d blocks of [3][J][7] (M, G1, G2 per dimension).
+//
+// d = 3: a workgroup owns a kLamT x kLamT column tile in dimensions 1 and 2
+// (halo included, so kLamB = kLamT - 6 outputs per edge) and a run of kLamC0
+// output planes along dimension 0. Each thread loads its column of c over the
+// run and its halo into registers once; then, kLamP planes at a time, the
+// dimension-0 contraction happens in registers and the dimension-1 and
+// dimension-2 passes go through LDS (two barriers per kLamP planes; the
+// planes of a step are independent, which hides LDS latency). Every c entry
+// is read (kLamT / kLamB)^2 (kLamC0 + 6) / kLamC0 times, from L2 mostly.
+constexpr int kLamT = 16;
+constexpr int kLamB = kLamT - 6;
+constexpr int kLamC0 = 8;
+constexpr int kLamP = 2;
+constexpr int kLamS = kLamT + 1;   // LDS row stride after dimension 1 (odd: rows fall on different banks)
+static_assert(kLamT * kLamT == kBlock, "one thread per column of the tile");
+static_assert(kLamC0 % kLamP == 0, "whole steps per run");
 
 template <typename T>
 __device__ __forceinline__ void band_row(const T* band, int J, int j, T (&m)[7], T (&g1)[7], T (&g2)[7]) {
@@ -605,80 +615,97 @@ __device__ __forceinline__ void band_row(const T* band, int J, int j, T (&m)[7],
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* c, T* out, const T* band, int J, int B1, int B2,
-                                                          int nt1, int nt2, T lam) {
-  __shared__ T sin_[7 * kLamH1 * kLamH2];   // staged c; later the dimension-1 results
-  __shared__ T s1[3 * kLamH1 * kLamH2];     // dimension-0 results T0, T1, T2
-  const int t2 = blockIdx.x % nt2;
-  const int t1 = (blockIdx.x / nt2) % nt1;
-  const int j0 = blockIdx.x / (nt2 * nt1);
-  const int H1 = B1 + 6, H2 = B2 + 6;
-  const int b1base = t1 * B1 - 3, b2base = t2 * B2 - 3;
+__global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* __restrict__ c, T* __restrict__ out,
+                                                          const T* __restrict__ band, int J, int B, int nt, T lam) {
+  __shared__ T s1[kLamP][3][kLamT * kLamT];   // T0, T1, T2 after dimension 0, per column
+  __shared__ T s2[kLamP][3][kLamB * kLamS];   // after dimension 1
+  __shared__ T sb[3][kLamC0][7];              // dimension-0 band rows (M, G1, G2) of the run
+  const int wg = xcd_block();   // an XCD takes whole runs of planes: the halos stay in its L2
+  const int t2 = wg % nt;
+  const int t1 = (wg / nt) % nt;
+  const int z0 = (wg / (nt * nt)) * kLamC0;
   const int64_t JJ = int64_t(J) * J;
-  for (int e = threadIdx.x; e < 7 * H1 * H2; e += kBlock) {
-    const int h2 = e % H2, h1 = (e / H2) % H1, o0 = e / (H2 * H1);
-    const int g0 = j0 + o0 - 3, g1 = b1base + h1, g2 = b2base + h2;
-    const bool ok = g0 >= 0 && g0 < J && g1 >= 0 && g1 < J && g2 >= 0 && g2 < J;
-    sin_[e] = ok ? c[int64_t(g0) * JJ + int64_t(g1) * J + g2] : T(0);
+  const int tid = threadIdx.x;
+  T v[kLamC0 + 6];
+  {
+    const int g1 = t1 * B - 3 + tid / kLamT, g2 = t2 * B - 3 + tid % kLamT;
+    const bool col = g1 >= 0 && g1 < J && g2 >= 0 && g2 < J;
+#pragma unroll
+    for (int i = 0; i < kLamC0 + 6; ++i) {
+      const int g0 = z0 - 3 + i;
+      v[i] = (col && g0 >= 0 && g0 < J) ? c[int64_t(g0) * JJ + int64_t(g1) * J + g2] : T(0);
+    }
+  }
+  // dimension-1 pass: thread -> (row b1a of the output tile, column h2a);
+  // dimension-2 pass: thread -> output (b1b, b2b)
+  const int b1a = tid / kLamT, h2a = tid % kLamT;
+  const int b1b = tid / B, b2b = tid % B;
+  const bool do1 = b1a < B && t1 * B + b1a < J;
+  const bool do2 = b1b < B && t1 * B + b1b < J && t2 * B + b2b < J;
+  T m1[7], p1[7], q1[7], m2[7], p2[7], q2[7];
+  band_row(band + size_t(3) * J * 7, J, do1 ? t1 * B + b1a : 0, m1, p1, q1);
+  band_row(band + size_t(6) * J * 7, J, do2 ? t2 * B + b2b : 0, m2, p2, q2);
+  const int nsteps = min(kLamC0, J - z0);
+  for (int e = tid; e < 3 * kLamC0 * 7; e += kBlock) {
+    const int kind = e / (kLamC0 * 7), i = (e / 7) % kLamC0, o = e % 7;
+    sb[kind][i][o] = i < nsteps ? band[(size_t(kind) * J + z0 + i) * 7 + o] : T(0);
   }
   __syncthreads();
-  {
-    T m[7], g1c[7], g2c[7];
-    band_row(band, J, j0, m, g1c, g2c);
-    for (int e = threadIdx.x; e < H1 * H2; e += kBlock) {
+#pragma unroll
+  for (int i = 0; i < kLamC0; i += kLamP) {
+    if (i >= nsteps) break;
+#pragma unroll
+    for (int p = 0; p < kLamP; ++p) {
       T a0 = T(0), a1 = T(0), a2 = T(0);
 #pragma unroll
       for (int o = 0; o < 7; ++o) {
-        const T v = sin_[o * H1 * H2 + e];
-        a0 += m[o] * v;
-        a1 += g1c[o] * v;
-        a2 += g2c[o] * v;
+        a0 += sb[0][i + p][o] * v[i + p + o];
+        a1 += sb[1][i + p][o] * v[i + p + o];
+        a2 += sb[2][i + p][o] * v[i + p + o];
       }
-      s1[e] = a0;
-      s1[H1 * H2 + e] = a1;
-      s1[2 * H1 * H2 + e] = a2;
+      s1[p][0][tid] = a0;
+      s1[p][1][tid] = a1;
+      s1[p][2][tid] = a2;
     }
-  }
-  __syncthreads();
-  const T* band1 = band + size_t(3) * J * 7;
-  T* s2 = sin_;   // [3][B1][H2]
-  for (int e = threadIdx.x; e < B1 * H2; e += kBlock) {
-    const int h2 = e % H2, b1 = e / H2;
-    const int j1 = t1 * B1 + b1;
-    if (j1 >= J) continue;
-    T m[7], g1c[7], g2c[7];
-    band_row(band1, J, j1, m, g1c, g2c);
-    T a0 = T(0), a1 = T(0), a2 = T(0);
+    __syncthreads();   // s1 complete; the previous step's readers of s2 are done
+    if (do1) {
 #pragma unroll
-    for (int o = 0; o < 7; ++o) {
-      const int q = (b1 + o) * H2 + h2;
-      const T v0 = s1[q], v1 = s1[H1 * H2 + q], v2 = s1[2 * H1 * H2 + q];
-      a0 += m[o] * v0;
-      a1 += m[o] * v1 + g1c[o] * v0;
-      a2 += m[o] * v2 + g2c[o] * v0 + T(2) * g1c[o] * v1;
-    }
-    s2[e] = a0;
-    s2[B1 * H2 + e] = a1;
-    s2[2 * B1 * H2 + e] = a2;
-  }
-  __syncthreads();
-  const T* band2 = band + size_t(6) * J * 7;
-  for (int e = threadIdx.x; e < B1 * B2; e += kBlock) {
-    const int b2 = e % B2, b1 = e / B2;
-    const int j1 = t1 * B1 + b1, j2 = t2 * B2 + b2;
-    if (j1 >= J || j2 >= J) continue;
-    T m[7], g1c[7], g2c[7];
-    band_row(band2, J, j2, m, g1c, g2c);
-    T a = T(0);
+      for (int p = 0; p < kLamP; ++p) {
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
 #pragma unroll
-    for (int o = 0; o < 7; ++o) {
-      const int q = b1 * H2 + b2 + o;
-      a += m[o] * s2[2 * B1 * H2 + q] + g2c[o] * s2[q] + T(2) * g1c[o] * s2[B1 * H2 + q];
+        for (int o = 0; o < 7; ++o) {
+          const int q = (b1a + o) * kLamT + h2a;
+          const T v0 = s1[p][0][q], v1 = s1[p][1][q], v2 = s1[p][2][q];
+          a0 += m1[o] * v0;
+          a1 += m1[o] * v1 + p1[o] * v0;
+          a2 += m1[o] * v2 + q1[o] * v0;
+          a3 += p1[o] * v1;
+        }
+        s2[p][0][b1a * kLamS + h2a] = a0;
+        s2[p][1][b1a * kLamS + h2a] = a1;
+        s2[p][2][b1a * kLamS + h2a] = a2 + T(2) * a3;
+      }
     }
-    out[int64_t(j0) * JJ + int64_t(j1) * J + j2] = lam * a;
+    __syncthreads();   // s2 complete; every reader of s1 is done
+    if (do2) {
+#pragma unroll
+      for (int p = 0; p < kLamP; ++p) {
+        if (i + p >= nsteps) break;
+        T a = T(0), b = T(0);
+#pragma unroll
+        for (int o = 0; o < 7; ++o) {
+          const int q = b1b * kLamS + b2b + o;
+          a += m2[o] * s2[p][2][q] + q2[o] * s2[p][0][q];
+          b += p2[o] * s2[p][1][q];
+        }
+        out[int64_t(z0 + i + p) * JJ + int64_t(t1 * B + b1b) * J + (t2 * B + b2b)] = lam * (a + T(2) * b);
+      }
+    }
   }
 }
 
+// d = 2: a workgroup stages a halo-extended kLam2H0 x kLam2H1 tile of c in
+// LDS and runs both passes there.
 constexpr int kLam2B0 = 8, kLam2B1 = 32;
 constexpr int kLam2H0 = kLam2B0 + 6, kLam2H1 = kLam2B1 + 6;
 
@@ -734,6 +761,8 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fused2(const T* c, T* out, co
   }
 }
 
+// lambda * diag(Lambda_g) from the diagonals of the 1D factors; `band` holds
+// [D][3][J][7] (each dimension has its own mesh width).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_lambda_diag(const double* band, int J, int64_t K,
                                                         double lam, double* out) {
@@ -1622,10 +1651,10 @@ hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipStream_t st) {
 template <typename T>
 hipError_t launch_lambda_fused(int D, const T* c, T* out, const T* band, int J, T lam, hipStream_t st) {
   if (D == 3) {
-    const int nt1 = (J + kLamB1 - 1) / kLamB1, nt2 = (J + kLamB2 - 1) / kLamB2;
-    const int B1 = (J + nt1 - 1) / nt1, B2 = (J + nt2 - 1) / nt2;   // <= kLamB1, kLamB2
-    hipLaunchKernelGGL(k_lambda_fused3<T>, dim3(unsigned(J * nt1 * nt2)), dim3(kBlock), 0, st, c, out, band, J, B1,
-                       B2, nt1, nt2, lam);
+    const int nt = (J + kLamB - 1) / kLamB, B = (J + nt - 1) / nt;   // B <= kLamB
+    const int nt0 = (J + kLamC0 - 1) / kLamC0;
+    hipLaunchKernelGGL(k_lambda_fused3<T>, dim3(unsigned(nt0 * nt * nt)), dim3(kBlock), 0, st, c, out, band, J, B, nt,
+                       lam);
     return hipGetLastError();
   }
   if (D == 2) {

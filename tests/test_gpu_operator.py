@@ -65,6 +65,28 @@ def test_apply_every_level_matrix_free_and_stencil(prob, mode):
         S.close()
 
 
+@pytest.mark.parametrize("N", [16, 32])
+def test_apply_lambda_dominated_d3(lib, N):
+    """lambda so large that lambda*Lambda dominates A_g (d = 3): the fused
+    Lambda kernel's column tiles, halos and runs of planes (J = 19 and 35
+    span several of each, with ragged last ones) against the oracle on every
+    level, FP64 and FP32."""
+    w = gc.uniform_case(3, 3001, N, 1e3, 7)
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"], stencil_mode=tsmg.TS_STENCIL_NONE)
+    try:
+        rng = np.random.default_rng(106)
+        for g in levels(S):
+            Ng = w["N"] >> (S.G - g)
+            c = rng.standard_normal(S.K(g))
+            ref = gc.oracle_apply(w, Ng, c)
+            assert gc.rel(S.apply(g, c).cpu().numpy(), ref) < 1e-12, g
+            c32 = c.astype(np.float32)
+            ref32 = gc.oracle_apply(w, Ng, c32.astype(np.float64))
+            assert gc.rel(S.apply(g, c32, fp32=True).cpu().numpy(), ref32) < 3e-5, g
+    finally:
+        S.close()
+
+
 def test_apply_fp32_finest_and_coarsest(prob):
     w, S = prob
     rng = np.random.default_rng(101)

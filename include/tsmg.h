@@ -144,7 +144,11 @@ ts_status ts_create(int d, int q, const int32_t* intervals, const double* lo,
                     const double* hi, int64_t n, const double* x, const double* y,
                     double lambda, const ts_options* opt, ts_problem** out);
 
-/* Releases every resource of the problem (synchronises its stream). NULL is a no-op. */
+/* Releases every resource of the problem (synchronises its stream). NULL is a no-op.
+ * Device memory goes back to the library's per-device cache, which later
+ * problems draw from; the cache keeps at most min(8 GiB, 1/16 of the
+ * device's memory) and is emptied into the device whenever an allocation
+ * fails. */
 void ts_destroy(ts_problem* p);
 
 /* Replaces the solve-time options of a problem: nu1, nu2, precision, max_iter,

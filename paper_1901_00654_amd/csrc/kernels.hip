@@ -1302,12 +1302,14 @@ __global__ __launch_bounds__(kBlock) void k_gemv(const double* A, int K, const T
 // (the Kronecker matvec of Alg. 2). lambda Lambda_g is added from the banded
 // 1D factors; the result is stored offset-major, S[o][k].
 
-// Moments of level g, accumulated (atomically; mom zeroed first) into the
-// axis-interleaved layout index = sum_p (c_p * 7 + e_p) * (7 N_g)^(D-1-p).
+// Moments of level g from the points, in the axis-interleaved layout
+// index = sum_p (c_p * 7 + e_p) * (7 N_g)^(D-1-p) (mom zeroed first).
 // Block (x, y, z): exponent tuples (e_1..e_{D-1}) starting at x * NR, level-g
 // cells y, y + gridDim.y, ..., and the z-th of gridDim.z chunks of each
 // cell's points. Threads are (tuple, stream): the NS = kBlock / NR streams
-// take every NS-th point of a staged tile.
+// take every NS-th point of a staged tile and are summed in LDS; a block
+// stores its sums, or adds them atomically when a cell is split over
+// gridDim.z > 1 blocks.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_level_moments(const double* t64, const uint32_t* cell,
                                                           const int32_t* off, int64_t n, int G, int g,
@@ -1318,6 +1320,7 @@ __global__ __launch_bounds__(kBlock) void k_level_moments(const double* t64, con
   constexpr int NR = NREST < kBlock ? NREST : kBlock;   // tuples per block
   constexpr int NS = kBlock / NR;                       // point streams per tuple
   __shared__ double pw[TILE][D][E];
+  __shared__ double red[kBlock][E];   // per-thread sums of a cell, reduced over the streams
   const int sh = G - g;
   const int S = D * sh;
   const uint32_t ncells = 1u << (D * g);
@@ -1367,19 +1370,66 @@ __global__ __launch_bounds__(kBlock) void k_level_moments(const double* t64, con
         }
       }
     }
-    if (active && b0 < b1) {
+    if (b0 < b1) {   // uniform in the block
+      if (active) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) red[threadIdx.x][e] = acc[e];
+      }
+      __syncthreads();
       int cc[D];
       morton_decode<D>(cidx, g, cc);
       const int64_t A = int64_t(E) << g;   // 7 N_g
-      int64_t idx_rest = 0, strideA0 = 1;
+      for (int w = threadIdx.x; w < NR * E; w += kBlock) {
+        const int tu = w / E, e = w % E;
+        const int rr = blockIdx.x * NR + tu;
+        if (rr >= NREST) continue;
+        double sum = 0.0;
+        for (int st = 0; st < NS; ++st) sum += red[st * NR + tu][e];
+        int64_t idx = int64_t(cc[0]) * E + e;
+        int rem = rr, ep[D];
 #pragma unroll
-      for (int p = 1; p < D; ++p) {
-        idx_rest = idx_rest * A + (int64_t(cc[p]) * E + er[p]);
-        strideA0 *= A;
+        for (int p = D - 1; p >= 1; --p) { ep[p] = rem % E; rem /= E; }
+#pragma unroll
+        for (int p = 1; p < D; ++p) idx = idx * A + (int64_t(cc[p]) * E + ep[p]);
+        if (gridDim.z > 1) atomicAdd(&mom[idx], sum);
+        else mom[idx] = sum;
       }
-#pragma unroll
-      for (int e = 0; e < E; ++e) atomicAdd(&mom[(int64_t(cc[0]) * E + e) * strideA0 + idx_rest], acc[e]);
+      __syncthreads();   // red is free again
     }
+  }
+}
+
+// Moments of the level g-1 cells from those of their children on level g,
+// along one dimension (D passes give all of them): with centred coordinates
+// u in a parent cell and u' in its child b (0: lower half, 1: upper half),
+// u = u'/2 + (2b-1)/4, so u^e = sum_{j<=e} C(e,j) 2^-j ((2b-1)/4)^(e-j) u'^j.
+// in: [outer][7 * 2Nc][inner], out: [outer][7 * Nc][inner], same axis
+// interleaving as k_level_moments.
+__global__ __launch_bounds__(kBlock) void k_moments_coarsen(const double* in, double* out, int Nc, int64_t outer,
+                                                            int64_t inner) {
+  constexpr int E = 7;
+  const int64_t total = outer * E * Nc * inner;
+  for (int64_t idx = int64_t(blockIdx.x) * kBlock + threadIdx.x; idx < total; idx += int64_t(gridDim.x) * kBlock) {
+    const int64_t i = idx % inner;
+    int64_t t = idx / inner;
+    const int e = int(t % E);
+    t /= E;
+    const int64_t C = t % Nc;
+    const int64_t o = t / Nc;
+    double sum = 0.0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double sb = b ? 0.25 : -0.25;
+      const double* src = in + ((o * 2 * Nc + 2 * C + b) * E) * inner + i;
+      double coef = ldexp(1.0, -e);   // C(e,j) 2^-j, exact
+      double shift = 1.0;             // sb^(e-j)
+      for (int j = e; j >= 0; --j) {
+        sum += coef * shift * src[int64_t(j) * inner];
+        coef = coef * 2.0 * j / double(e - j + 1);
+        shift *= sb;
+      }
+    }
+    out[idx] = sum;
   }
 }
 
@@ -1969,6 +2019,14 @@ hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, 
     case 5: hipLaunchKernelGGL(k_level_moments<5>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_coarsen(const double* in, double* out, int Nc, int64_t outer, int64_t inner,
+                                  hipStream_t st) {
+  const int64_t total = outer * 7 * Nc * inner;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_moments_coarsen, dim3(blocks_for(total)), dim3(kBlock), 0, st, in, out, Nc, outer, inner);
   return hipGetLastError();
 }
 

@@ -7,7 +7,12 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
+#include <future>
+#include <map>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/tsmg.h"
@@ -20,6 +25,100 @@ thread_local std::string g_last_error;
 thread_local MemCount g_mem;
 
 void set_error(const std::string& m) { g_last_error = m; }
+
+// ---------------------------------------------------------------------------
+// Device memory cache. Sizes are rounded up (64 KiB steps to 16 MiB, 2 MiB
+// steps above) and a cached block is reused for a request of at least 4/5
+// of its size. The cache holds at most min(8 GiB, 1/16 of the device) per
+// device. It is never torn down: the blocks live until the process ends.
+namespace {
+struct DevicePool {
+  std::multimap<size_t, void*> free_blocks;   // size -> block
+  size_t cached = 0;
+  size_t cap = 0;
+};
+struct Pool {
+  std::mutex m;
+  std::map<int, DevicePool> dev;
+  std::unordered_map<void*, std::pair<int, size_t>> live;   // block -> (device, size)
+};
+Pool& pool() {
+  static Pool* p = new Pool;   // not destroyed at exit: the runtime may be gone by then
+  return *p;
+}
+size_t pool_round(size_t b) {
+  const size_t q = b <= (size_t(16) << 20) ? (size_t(64) << 10) : (size_t(2) << 20);
+  return (b + q - 1) / q * q;
+}
+}  // namespace
+
+void* pool_alloc(size_t bytes) {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "get device");
+  const size_t sz = pool_round(bytes);
+  Pool& P = pool();
+  std::vector<void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(P.m);
+    DevicePool& D = P.dev[dev];
+    auto it = D.free_blocks.lower_bound(sz);
+    if (it != D.free_blocks.end() && it->first / 5 * 4 <= sz) {
+      void* p = it->second;
+      D.cached -= it->first;
+      P.live[p] = {dev, it->first};
+      D.free_blocks.erase(it);
+      return p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, sz);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    {
+      std::lock_guard<std::mutex> lk(P.m);
+      DevicePool& D = P.dev[dev];
+      for (auto& b : D.free_blocks) drop.push_back(b.second);
+      D.free_blocks.clear();
+      D.cached = 0;
+    }
+    for (void* b : drop) (void)hipFree(b);
+    e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{TS_ENOMEM, "hipMalloc of " + std::to_string(sz) + " bytes failed"};
+    }
+  }
+  std::lock_guard<std::mutex> lk(P.m);
+  P.live[p] = {dev, sz};
+  return p;
+}
+
+void pool_release(void* p) {
+  Pool& P = pool();
+  bool free_now = std::uncaught_exceptions() > 0;
+  {
+    std::lock_guard<std::mutex> lk(P.m);
+    auto it = P.live.find(p);
+    if (it == P.live.end()) return;
+    const int dev = it->second.first;
+    const size_t sz = it->second.second;
+    P.live.erase(it);
+    DevicePool& D = P.dev[dev];
+    if (D.cap == 0) {
+      size_t fr = 0, tot = 0;
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      if (cur == dev && hipMemGetInfo(&fr, &tot) == hipSuccess) D.cap = std::min(size_t(8) << 30, tot / 16);
+      else D.cap = size_t(1) << 30;
+    }
+    if (!free_now && D.cached + sz <= D.cap) {
+      D.free_blocks.emplace(sz, p);
+      D.cached += sz;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
 
 void hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return;
@@ -215,20 +314,25 @@ static DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out
 // - packed (d >= 4, where staging and flushing a (2^tb+3)^d patch twice
 //   costs more): whole tiles, cut only when longer than ppb, are packed into
 //   workgroups of at most ppb points.
-static void build_worklist(Problem* P, int g, const std::vector<int32_t>& off) {
-  const bool split = P->d <= 3;
-  Level& L = P->lev[g];
-  const int D = P->d;
-  const int sh = P->G - g;
-  const int tb = L.tb;
+struct WorkListHost {
+  std::vector<int32_t> first;   // per workgroup: its first chunk (one past the last entry: the end)
+  std::vector<int4> chunks;
+  std::vector<uint32_t> items;
+};
+
+// Host side only (no device calls), so that it can run on a host thread.
+static WorkListHost make_worklist(int D, int G, int g, int tb, int64_t ppb, const std::vector<int32_t>& off) {
+  const bool split = D <= 3;
+  const int sh = G - g;
   const int Q = kItemQ[D];
-  const int64_t ch = P->ppb;
+  const int64_t ch = ppb;
   const int cells_in_tile = 1 << (D * tb);
   const int64_t ntiles = int64_t(1) << (D * (g - tb));
   auto cell_start = [&](int64_t c) { return int64_t(off[size_t(c << (D * sh))]); };   // level-g Morton cell c
-  std::vector<int32_t> first;
-  std::vector<int4> chunks;
-  std::vector<uint32_t> items;
+  WorkListHost w;
+  std::vector<int32_t>& first = w.first;
+  std::vector<int4>& chunks = w.chunks;
+  std::vector<uint32_t>& items = w.items;
   int64_t wg_points = 0;
   for (int64_t t = 0; t < ntiles; ++t) {
     const int64_t c0 = t << (D * tb);
@@ -270,6 +374,14 @@ static void build_worklist(Problem* P, int g, const std::vector<int32_t>& off) {
   first.push_back(int32_t(chunks.size()));
   chunks.push_back(make_int4(0, 0, int(items.size()), 0));
   if (items.empty()) items.push_back(0u);
+  return w;
+}
+
+static void upload_worklist(Problem* P, int g, const WorkListHost& w) {
+  Level& L = P->lev[g];
+  const std::vector<int32_t>& first = w.first;
+  const std::vector<int4>& chunks = w.chunks;
+  const std::vector<uint32_t>& items = w.items;
   hipStream_t st = P->stream;
   L.wl_groups = int(first.size()) - 1;
   L.wl_first.alloc(first.size());
@@ -565,7 +677,9 @@ static double lanczos_theta(Problem* P, int g, int steps) {
 // Assembles A_g of level g as a 7^d-point stencil: level moments, d
 // Kronecker passes with the pair table, then lambda Lambda_g and the
 // offset-major layout.
-static void build_stencil(Problem* P, int g) {
+// mom: on entry the moments of level g if the caller has them (from the level
+// above), else empty; on return the moments of level g-1 if want_coarser.
+static void build_stencil(Problem* P, int g, DevBuf<double>& mom, bool want_coarser) {
   Level& L = P->lev[g];
   const int D = P->d, N = L.N, J = L.J;
   int64_t NO = 1, in_sz = 1, max_sz = 0;
@@ -575,23 +689,51 @@ static void build_stencil(Problem* P, int g) {
     int64_t sz = in_sz;
     for (int p = 0; p < D; ++p) { sz = sz / (int64_t(7) * N) * (int64_t(7) * J); max_sz = std::max(max_sz, sz); }
   }
-  DevBuf<double> bufA, bufB, ctab;
-  bufA.alloc(size_t(max_sz));
-  bufB.alloc(size_t(max_sz));
+  DevBuf<double> bufA, bufB, ctab, coarser;
   std::vector<double> ct;
   pair_table(ct);
   ctab.alloc(ct.size());
   hip_check(hipMemcpyAsync(ctab.p, ct.data(), ct.size() * sizeof(double), hipMemcpyHostToDevice, P->stream),
             "upload");
-  hip_check(launch_fill<double>(bufA.p, 0.0, in_sz, P->stream), "fill");
-  hip_check(launch_level_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, g, bufA.p, P->stream), "moments");
+  const double* src = mom.p;
+  if (!src) {
+    bufA.alloc(size_t(max_sz));
+    hip_check(launch_fill<double>(bufA.p, 0.0, in_sz, P->stream), "fill");
+    hip_check(launch_level_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, g, bufA.p, P->stream), "moments");
+    src = bufA.p;
+  }
+  bufB.alloc(size_t(max_sz));
+  if (want_coarser && g > 1) {
+    // level g-1 moments, one dimension at a time through two regions of bufB
+    // (each pass halves the size)
+    const int Nc = N / 2;
+    int64_t csz = 1;
+    for (int p = 0; p < D; ++p) csz *= int64_t(7) * Nc;
+    coarser.alloc(size_t(csz));
+    double* region[2] = {bufB.p, bufB.p + in_sz / 2};
+    const double* cin = src;
+    for (int p = 0; p < D; ++p) {
+      int64_t outer = 1, inner = 1;
+      for (int q = 0; q < p; ++q) outer *= int64_t(7) * Nc;
+      for (int q = p + 1; q < D; ++q) inner *= int64_t(7) * N;
+      double* cout = (p == D - 1) ? coarser.p : region[p % 2];
+      hip_check(launch_moments_coarsen(cin, cout, Nc, outer, inner, P->stream), "coarsen moments");
+      cin = cout;
+    }
+  }
   double* cur = bufA.p;
   double* nxt = bufB.p;
   for (int p = 0; p < D; ++p) {
     int64_t outer = 1, inner = 1;
     for (int q = 0; q < p; ++q) outer *= int64_t(7) * J;
     for (int q = p + 1; q < D; ++q) inner *= int64_t(7) * N;
-    hip_check(launch_stencil_pass(cur, nxt, ctab.p, N, outer, inner, P->stream), "stencil pass");
+    hip_check(launch_stencil_pass(p == 0 ? src : cur, nxt, ctab.p, N, outer, inner, P->stream), "stencil pass");
+    if (p == 0 && !bufA.p) {   // the moments came from the caller: trade them for the second buffer
+      hip_check(hipStreamSynchronize(P->stream), "sync");
+      mom.reset();
+      bufA.alloc(size_t(max_sz));
+      cur = bufA.p;
+    }
     std::swap(cur, nxt);
   }
   L.S64.alloc(size_t(NO * L.K));
@@ -611,6 +753,7 @@ static void build_stencil(Problem* P, int g) {
   hip_check(hipMemcpyAsync(L.soffs.p, offs.data(), offs.size() * sizeof(int32_t), hipMemcpyHostToDevice, P->stream),
             "upload");
   hip_check(hipStreamSynchronize(P->stream), "sync");   // temporaries and host tables go out of scope
+  mom = std::move(coarser);
   L.stencil = true;
 }
 
@@ -663,7 +806,9 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
     // level 1 always carries its stencil: A_1 is expanded from it
     if (g == 1 || st) {
       stencils += ipow(7, d) * K * 12 + ipow(7, d) * 4;
-      stencil_tmp = std::max(stencil_tmp, 2 * ipow(7 * int64_t(J), d) * 8 + (1 << 16));
+      // two pass buffers, plus the moments handed on to level g-1
+      const int64_t coarser = g > 1 ? ipow(7 * int64_t(1 << (g - 1)), d) * 8 : 0;
+      stencil_tmp = std::max(stencil_tmp, 2 * ipow(7 * int64_t(J), d) * 8 + coarser + (1 << 16));
     }
   }
   const int64_t K1 = ipow(2 + kDeg, d);
@@ -685,7 +830,8 @@ static void build_coarse(Problem* P) {
   const int64_t K1 = L1.K;
   P->K1 = int(K1);
   if (!L1.S64.p) {
-    build_stencil(P, 1);
+    DevBuf<double> none;
+    build_stencil(P, 1, none, false);
     L1.stencil = (P->opt.stencil_mode != 1);
   }
   DevBuf<double> row, col, piv;
@@ -875,26 +1021,42 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     P->v32.alloc(size_t(KG));
     P->d32.alloc(size_t(KG));
 
-    // --- assembled stencils for the levels where they pay (same A_g)
+    // --- assembled stencils for the levels where they pay (same A_g), and
+    // the point pass's work lists on the other levels, built on a host
+    // thread meanwhile
     {
       const double budget = stencil_budget_for(stencil_budget);
-      for (int g = 1; g <= G; ++g)
-        if (want_stencil(d, P->lev[g].J, n, P->opt.stencil_mode, budget)) build_stencil(P, g);
-    }
-
-    // --- work lists of the point pass on the matrix-free levels
-    {
-      std::vector<int32_t> off_h;
+      std::vector<char> want(size_t(G) + 1, 0);
+      bool matrix_free = false;
       for (int g = 1; g <= G; ++g) {
-        if (P->lev[g].stencil) continue;
-        if (off_h.empty()) {
-          off_h.resize(size_t((int64_t(1) << (G * d)) + 1));
-          hip_check(hipMemcpyAsync(off_h.data(), P->off.p, off_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st),
-                    "download");
-          hip_check(hipStreamSynchronize(st), "sync");
-        }
-        build_worklist(P, g, off_h);
+        want[size_t(g)] = want_stencil(d, P->lev[g].J, n, P->opt.stencil_mode, budget);
+        matrix_free = matrix_free || !want[size_t(g)];
       }
+      std::vector<int32_t> off_h;
+      if (matrix_free) {
+        off_h.resize(size_t((int64_t(1) << (G * d)) + 1));
+        hip_check(hipMemcpyAsync(off_h.data(), P->off.p, off_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st),
+                  "download");
+        hip_check(hipStreamSynchronize(st), "sync");
+      }
+      std::vector<int> tbs(size_t(G) + 1);
+      for (int g = 1; g <= G; ++g) tbs[size_t(g)] = P->lev[g].tb;
+      const int64_t ppb = P->ppb;
+      auto lists = std::async(std::launch::async, [&want, &off_h, tbs, ppb, d, G]() {
+        std::vector<WorkListHost> r(size_t(G) + 1);
+        for (int g = 1; g <= G; ++g)
+          if (!want[size_t(g)]) r[size_t(g)] = make_worklist(d, G, g, tbs[size_t(g)], ppb, off_h);
+        return r;
+      });
+      // finest first: each level's moments give the next coarser level's
+      DevBuf<double> mom;
+      for (int g = G; g >= 1; --g) {
+        if (!want[size_t(g)]) { mom.reset(); continue; }
+        build_stencil(P, g, mom, g > 1 && want[size_t(g) - 1]);
+      }
+      const std::vector<WorkListHost> wl = lists.get();
+      for (int g = 1; g <= G; ++g)
+        if (!want[size_t(g)]) upload_worklist(P, g, wl[size_t(g)]);
     }
 
     // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)

@@ -32,8 +32,19 @@ struct MemCount {
 };
 extern thread_local MemCount g_mem;
 
-// Owning device buffer (freed on destruction). Allocation failure throws
-// Error{TS_ENOMEM}.
+// Device memory cache of the library (per device, shared by all problems
+// and threads). pool_alloc returns a block of at least `bytes`, reusing one
+// released earlier when one of a close size is cached, else from hipMalloc
+// (after emptying the cache if hipMalloc fails); throws Error{TS_ENOMEM}.
+// pool_release caches the block, or frees it when the cache is full. A
+// block may be released only once no queued device work uses it.
+void* pool_alloc(size_t bytes);
+void pool_release(void* p);
+
+// Owning device buffer, returned to the cache on destruction. Every owner
+// synchronises the stream its buffers were used on before releasing them;
+// a buffer released while an exception unwinds is freed with hipFree
+// instead, which waits for the device.
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
@@ -50,19 +61,14 @@ struct DevBuf {
   void alloc(size_t count) {
     reset();
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
-    if (e != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      throw Error{TS_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
-    }
+    p = static_cast<T*>(pool_alloc(count * sizeof(T)));
     n = count;
     g_mem.live += int64_t(count * sizeof(T));
     if (g_mem.live > g_mem.peak) g_mem.peak = g_mem.live;
   }
   void reset() {
     if (p) {
-      (void)hipFree(p);
+      pool_release(p);
       g_mem.live -= int64_t(n * sizeof(T));
     }
     p = nullptr;

@@ -1214,15 +1214,18 @@ __global__ __launch_bounds__(kBlock) void k_eval(const double* alpha, const doub
 
 // ---------------------------------------------------------------------------
 // Coarse matrix A_1 (Sec. 3.2.4): the dense K_1 x K_1 matrix expanded from
-// the level-1 stencil (A1 zeroed first), then inverted by Gauss-Jordan.
+// the level-1 stencil (A1 zeroed first), then inverted by Gauss-Jordan. The
+// stencil holds the upper half of the offsets (see k_stencil_finalize); each
+// entry fills A[k][l] and its mirror A[l][k].
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_dense_from_stencil(const double* S, int J, int64_t K, double* A) {
   const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   int NO = 1;
 #pragma unroll
   for (int p = 0; p < D; ++p) NO *= 7;
-  if (t >= int64_t(NO) * K) return;
-  const int oidx = int(t / K);
+  const int NH = (NO + 1) / 2;
+  if (t >= int64_t(NH) * K) return;
+  const int oidx = NO / 2 + int(t / K);
   const int64_t k = t % K;
   int64_t rk = k, l = 0, stride = 1;
   int ro = oidx;
@@ -1236,7 +1239,10 @@ __global__ __launch_bounds__(kBlock) void k_dense_from_stencil(const double* S, 
     l += (kp + op) * stride;
     stride *= J;
   }
-  if (inside) A[k * K + l] = S[t];
+  if (inside) {
+    A[k * K + l] = S[t];
+    A[l * K + k] = S[t];
+  }
 }
 
 // In-place Gauss-Jordan inversion without pivoting (A_1 is SPD), step k:
@@ -1459,8 +1465,11 @@ __global__ __launch_bounds__(kBlock) void k_stencil_pass(const double* in, doubl
   out[t] = sacc;
 }
 
-// S[o][k] = (data stencil in the interleaved layout) + lambda Lambda_g[k, k+o];
-// entries whose neighbour falls outside the grid are zero.
+// S[h][k] = (data stencil in the interleaved layout) + lambda Lambda_g[k, k+o]
+// for the offsets o = NO/2 + h, h = 0..NO/2 (the centre and the offsets after
+// it in the base-7 order, i.e. the flat offset is >= 0): A_g is symmetric, so
+// the other half is A[k][k-o] = S[h][k-o]. Entries whose neighbour falls
+// outside the grid are zero.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_stencil_finalize(const double* inter, const double* band, int J,
                                                              int64_t K, double lam, double* S64, float* S32) {
@@ -1468,8 +1477,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_finalize(const double* inter
   int NO = 1;
 #pragma unroll
   for (int p = 0; p < D; ++p) NO *= 7;
-  if (t >= int64_t(NO) * K) return;
-  const int oidx = int(t / K);
+  if (t >= int64_t((NO + 1) / 2) * K) return;
+  const int oidx = NO / 2 + int(t / K);
   const int64_t k = t % K;
   int kp[D], op[D];
   {
@@ -1524,15 +1533,23 @@ __global__ __launch_bounds__(kBlock) void k_stencil_finalize(const double* inter
   S32[t] = float(v);
 }
 
-// v = A_g x with the stored stencil, v[k] = sum_o S[o][k] x[k + off(o)], then
-// the epilogue: out = v (kStPlain), out = x + w (b - v) (kStJacobi, one damped
-// Jacobi sweep of Alg. 6; out must not alias x), or out = v - b (kStResidual).
-// A block takes 36 rows; thread (plane, row) sums the 7^(D-1) stencil points
-// whose first-dimension offset is `plane`, and the 7 plane sums are added in
-// LDS. A neighbour outside the grid has S = 0; its index is clamped into range
-// so the (finite) value read there is multiplied by zero.
+// v = A_g x with the stored half stencil (k_stencil_finalize):
+//   v[k] = S[0][k] x[k] + sum_{h>=1} (S[h][k] x[k + off[h]] + S[h][k - off[h]] x[k - off[h]]),
+// the last term being A[k][k-off] = A[k-off][k]; then the epilogue: out = v
+// (kStPlain), out = x + w (b - v) (kStJacobi, one damped Jacobi sweep of
+// Alg. 6; out must not alias x), or out = v - b (kStResidual). A neighbour
+// outside the grid has S = 0 (its index is clamped into range, so the finite
+// value read there is multiplied by zero); a mirrored row index below zero is
+// skipped.
 enum StencilEpilogue : int { kStPlain = 0, kStJacobi = 1, kStResidual = 2, kStJacobiZero = 3 };
 constexpr int kStRows = kBlock / 7;   // 36 rows per block
+
+template <int D>
+constexpr int stencil_half() {
+  int no = 1;
+  for (int p = 0; p < D; ++p) no *= 7;
+  return (no + 1) / 2;
+}
 
 // Input value at flat index i: x[i], or for kStJacobiZero the first sweep
 // from zero, w[i] b[i] (x is not read).
@@ -1553,38 +1570,38 @@ __device__ __forceinline__ void stencil_out(const T* x, T* out, const T* b, cons
   }
 }
 
-// Rows k of the level in blocks of 36; each of the 7 first-dimension offset
-// planes of a row (7^(D-1) stencil points each) is one thread; the planes
-// are summed in LDS. For levels with many rows (streams the stencil once).
+// Stored offsets h and their mirrors, for row k.
+template <typename T, int EPI>
+__device__ __forceinline__ void stencil_pair(const T* S, const int32_t* offs, const T* x, const T* b, const T* w,
+                                             int64_t K, int64_t k, int h, T& a0, T& a1) {
+  const int64_t off = offs[h];
+  int64_t i = k + off;
+  i = i >= K ? K - 1 : i;
+  a0 += S[int64_t(h) * K + k] * stencil_in<T, EPI>(x, b, w, i);
+  const int64_t j = k - off;
+  if (h > 0 && j >= 0) a1 += S[int64_t(h) * K + j] * stencil_in<T, EPI>(x, b, w, j);
+}
+
+// Rows k of the level in blocks of 36; the stored offsets are dealt to 7
+// groups of threads per row and the group sums are added in LDS. For levels
+// with many rows (streams the stored half once; its mirror reads come back
+// from cache).
 template <typename T, int D, int EPI>
 __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int32_t* offs, const T* x, T* out,
                                                           const T* b, const T* w, int64_t K) {
-  constexpr int NI = (D == 1) ? 1 : (D == 2 ? 7 : (D == 3 ? 49 : (D == 4 ? 343 : 2401)));
+  constexpr int NH = stencil_half<D>();
+  constexpr int PERG = (NH + 6) / 7;
   __shared__ T part[7][kStRows];
-  const int plane = threadIdx.x / kStRows;
+  const int grp = threadIdx.x / kStRows;
   const int rl = threadIdx.x % kStRows;
   const int64_t k = int64_t(blockIdx.x) * kStRows + rl;
-  if (plane < 7) {
+  if (grp < 7) {
     T a0 = T(0), a1 = T(0);
     if (k < K) {
-      const int obase = plane * NI;
-      int j = 0;
-      for (; j + 1 < NI; j += 2) {
-        const int o0 = obase + j, o1 = o0 + 1;
-        int64_t i0 = k + offs[o0], i1 = k + offs[o1];
-        i0 = i0 < 0 ? 0 : (i0 >= K ? K - 1 : i0);
-        i1 = i1 < 0 ? 0 : (i1 >= K ? K - 1 : i1);
-        a0 += S[int64_t(o0) * K + k] * stencil_in<T, EPI>(x, b, w, i0);
-        a1 += S[int64_t(o1) * K + k] * stencil_in<T, EPI>(x, b, w, i1);
-      }
-      if (j < NI) {
-        const int o0 = obase + j;
-        int64_t i0 = k + offs[o0];
-        i0 = i0 < 0 ? 0 : (i0 >= K ? K - 1 : i0);
-        a0 += S[int64_t(o0) * K + k] * stencil_in<T, EPI>(x, b, w, i0);
-      }
+      const int h1 = min(NH, (grp + 1) * PERG);
+      for (int h = grp * PERG; h < h1; ++h) stencil_pair<T, EPI>(S, offs, x, b, w, K, k, h, a0, a1);
     }
-    part[plane][rl] = a0 + a1;
+    part[grp][rl] = a0 + a1;
   }
   __syncthreads();
   if (threadIdx.x < kStRows && k < K) {
@@ -1596,9 +1613,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int3
 }
 
 // The same product for levels with few rows, where the kernel above is
-// latency-bound (49 or more dependent iterations per thread): 8 rows per
-// block, 32 threads per row, each taking every 32nd stencil point, summed by
-// a tree in LDS.
+// latency-bound: 8 rows per block, 32 threads per row, each taking every
+// 32nd stored offset, summed by a tree in LDS.
 constexpr int kStSmallRows = 8;
 constexpr int kStSmallCols = kBlock / kStSmallRows;
 constexpr int64_t kStSmallMaxK = 16384;
@@ -1606,25 +1622,21 @@ constexpr int64_t kStSmallMaxK = 16384;
 template <typename T, int D, int EPI>
 __global__ __launch_bounds__(kBlock) void k_stencil_apply_small(const T* S, const int32_t* offs, const T* x, T* out,
                                                                 const T* b, const T* w, int64_t K) {
-  constexpr int NO = (D == 1) ? 7 : (D == 2 ? 49 : (D == 3 ? 343 : (D == 4 ? 2401 : 16807)));
-  constexpr int PER = (NO + kStSmallCols - 1) / kStSmallCols;
+  constexpr int NH = stencil_half<D>();
+  constexpr int PER = (NH + kStSmallCols - 1) / kStSmallCols;
   __shared__ T part[kStSmallCols][kStSmallRows];
   const int r = threadIdx.x % kStSmallRows;
   const int c = threadIdx.x / kStSmallRows;
   const int64_t k = int64_t(blockIdx.x) * kStSmallRows + r;
-  T a = T(0);
+  T a0 = T(0), a1 = T(0);
   if (k < K) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int o = c + q * kStSmallCols;
-      if (o < NO) {
-        int64_t i = k + offs[o];
-        i = i < 0 ? 0 : (i >= K ? K - 1 : i);
-        a += S[int64_t(o) * K + k] * stencil_in<T, EPI>(x, b, w, i);
-      }
+      const int h = c + q * kStSmallCols;
+      if (h < NH) stencil_pair<T, EPI>(S, offs, x, b, w, K, k, h, a0, a1);
     }
   }
-  part[c][r] = a;
+  part[c][r] = a0 + a1;
   __syncthreads();
 #pragma unroll
   for (int h = kStSmallCols / 2; h >= 1; h >>= 1) {
@@ -1961,7 +1973,7 @@ hipError_t launch_eval(int D, const double* alpha, const double* xq, int64_t m, 
 hipError_t launch_dense_from_stencil(int D, const double* S, int J, int64_t K, double* A, hipStream_t st) {
   int64_t NO = 1;
   for (int p = 0; p < D; ++p) NO *= 7;
-  const unsigned g = blocks_for(NO * K);
+  const unsigned g = blocks_for((NO + 1) / 2 * K);   // the stored half
   switch (D) {
     case 1: hipLaunchKernelGGL(k_dense_from_stencil<1>, dim3(g), dim3(kBlock), 0, st, S, J, K, A); break;
     case 2: hipLaunchKernelGGL(k_dense_from_stencil<2>, dim3(g), dim3(kBlock), 0, st, S, J, K, A); break;
@@ -2041,7 +2053,7 @@ hipError_t launch_stencil_finalize(int D, const double* inter, const double* ban
                                    double* S64, float* S32, hipStream_t st) {
   int64_t NO = 1;
   for (int p = 0; p < D; ++p) NO *= 7;
-  const unsigned g = blocks_for(NO * K);
+  const unsigned g = blocks_for((NO + 1) / 2 * K);   // the stored half
   switch (D) {
     case 1: hipLaunchKernelGGL(k_stencil_finalize<1>, dim3(g), dim3(kBlock), 0, st, inter, band, J, K, lam, S64, S32); break;
     case 2: hipLaunchKernelGGL(k_stencil_finalize<2>, dim3(g), dim3(kBlock), 0, st, inter, band, J, K, lam, S64, S32); break;

@@ -736,18 +736,19 @@ static void build_stencil(Problem* P, int g, DevBuf<double>& mom, bool want_coar
     }
     std::swap(cur, nxt);
   }
-  L.S64.alloc(size_t(NO * L.K));
-  L.S32.alloc(size_t(NO * L.K));
+  const int64_t NH = (NO + 1) / 2;   // stored half of the offsets (A_g is symmetric)
+  L.S64.alloc(size_t(NH * L.K));
+  L.S32.alloc(size_t(NH * L.K));
   hip_check(launch_stencil_finalize(D, cur, L.band64.p, J, L.K, P->lam, L.S64.p, L.S32.p, P->stream), "finalize");
-  std::vector<int32_t> offs(static_cast<size_t>(NO));
-  for (int64_t o = 0; o < NO; ++o) {
-    int64_t rem = o, off = 0, stride = 1;
+  std::vector<int32_t> offs(static_cast<size_t>(NH));   // flat offsets (>= 0) of the stored half
+  for (int64_t h = 0; h < NH; ++h) {
+    int64_t rem = NO / 2 + h, off = 0, stride = 1;
     for (int p = D - 1; p >= 0; --p) {
       off += (rem % 7 - 3) * stride;
       rem /= 7;
       stride *= J;
     }
-    offs[size_t(o)] = int32_t(off);
+    offs[size_t(h)] = int32_t(off);
   }
   L.soffs.alloc(offs.size());
   hip_check(hipMemcpyAsync(L.soffs.p, offs.data(), offs.size() * sizeof(int32_t), hipMemcpyHostToDevice, P->stream),
@@ -766,7 +767,7 @@ static bool want_stencil(int d, int J, int64_t n, int mode, double budget) {
   double NO = 1.0, P4 = 1.0, K = 1.0, transient = 1.0;
   for (int p = 0; p < d; ++p) { NO *= 7.0; P4 *= 4.0; K *= J; transient *= 7.0 * J; }
   const double entries = NO * K;
-  const double bytes = entries * 12.0 + 2.0 * transient * 8.0;
+  const double bytes = (NO + 1.0) / 2.0 * K * 12.0 + 2.0 * transient * 8.0;   // the stored half, FP64 + FP32
   if (bytes > budget) return false;
   if (mode == 2) return true;
   return entries * 1.6e-12 < double(n) * P4 * 0.5e-12;
@@ -805,7 +806,7 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
     }
     // level 1 always carries its stencil: A_1 is expanded from it
     if (g == 1 || st) {
-      stencils += ipow(7, d) * K * 12 + ipow(7, d) * 4;
+      stencils += (ipow(7, d) + 1) / 2 * (K * 12 + 4);   // the stored half
       // two pass buffers, plus the moments handed on to level g-1
       const int64_t coarser = g > 1 ? ipow(7 * int64_t(1 << (g - 1)), d) * 8 : 0;
       stencil_tmp = std::max(stencil_tmp, 2 * ipow(7 * int64_t(J), d) * 8 + coarser + (1 << 16));

@@ -89,9 +89,9 @@ struct Level {
   DevBuf<double> a64, b64, t64;    // V-cycle iterate, right-hand side, A x work vector
   DevBuf<float> a32, b32, t32;
   bool stencil = false;            // A_g assembled as a 7^d-point stencil
-  DevBuf<double> S64;              // [7^d][K] offset-major stencil
+  DevBuf<double> S64;              // [(7^d+1)/2][K] offset-major stencil, upper half of the offsets
   DevBuf<float> S32;
-  DevBuf<int32_t> soffs;           // [7^d] flat index offset of each stencil point
+  DevBuf<int32_t> soffs;           // [(7^d+1)/2] flat index offset (>= 0) of each stored stencil point
   // work list of the point pass (levels applied matrix-free)
   DevBuf<int32_t> wl_first;        // [workgroups + 1]
   DevBuf<int4> wl_chunks;          // [chunks + 1]

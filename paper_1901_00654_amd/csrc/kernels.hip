@@ -1594,7 +1594,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int3
   __shared__ T part[7][kStRows];
   const int grp = threadIdx.x / kStRows;
   const int rl = threadIdx.x % kStRows;
-  const int64_t k = int64_t(blockIdx.x) * kStRows + rl;
+  // contiguous row ranges per XCD: a stored entry and its mirrored read meet in one L2
+  const int64_t k = int64_t(xcd_block()) * kStRows + rl;
   if (grp < 7) {
     T a0 = T(0), a1 = T(0);
     if (k < K) {

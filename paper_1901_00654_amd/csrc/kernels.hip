@@ -355,9 +355,31 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
     lead_off += aq * st[q];
   }
 
+  // level-g positions in the cell of points [from, from + m) to s_tt[p][0..m)
+  auto stage_points = [&](int64_t from, int m) {
+    for (int idx = threadIdx.x; idx < m; idx += kBlock) {
+      const size_t i = size_t(from) + size_t(idx);
+      const uint32_t cf = a.cell[i];
+#pragma unroll
+      for (int p = 0; p < D; ++p) {
+        const uint32_t cfp = (cf >> (a.G * (D - 1 - p))) & maskN;
+        s_tt[p * a.ppb + idx] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + i]) * scale;
+      }
+    }
+  };
+
   const int wg = xcd_block();
   int64_t pos = 0, end = 0, seg_end = 0;
   int c_cur = 0, c_end = 0;
+  // A split work list (d <= 3) gives workgroup wg exactly the points
+  // [wg ppb, (wg+1) ppb): they are staged once, up front, while the chunk
+  // descriptors are still loading.
+  constexpr bool STAGE_ONCE = WL && D <= 3;
+  int64_t wbase = 0;
+  if constexpr (STAGE_ONCE) {
+    wbase = int64_t(wg) * a.ppb;
+    stage_points(wbase, int(min(a.n, wbase + int64_t(a.ppb)) - wbase));
+  }
   if constexpr (WL) {
     c_cur = a.wl_first[wg];
     c_end = a.wl_first[wg + 1];
@@ -406,17 +428,9 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       lo_rel = int(lo - pos);
       nch = (cnt + Q - 1) / Q;
     }
-    // stage the chunk's points (one coalesced pass)
-    const int mseg = int(seg_end - pos);
-    for (int idx = threadIdx.x; idx < mseg; idx += kBlock) {
-      const size_t i = size_t(pos) + size_t(idx);
-      const uint32_t cf = a.cell[i];
-#pragma unroll
-      for (int p = 0; p < D; ++p) {
-        const uint32_t cfp = (cf >> (a.G * (D - 1 - p))) & maskN;
-        s_tt[p * a.ppb + idx] = (T(double(cfp & maskSh)) + tfrac[size_t(p) * size_t(a.n) + i]) * scale;
-      }
-    }
+    // stage the chunk's points (one coalesced pass), unless staged up front
+    if constexpr (!STAGE_ONCE) stage_points(pos, int(seg_end - pos));
+    const int sbase = STAGE_ONCE ? int(pos - wbase) : 0;   // the chunk's first point in s_tt
     if (seg_first) {
       morton_decode<D>(tile, a.g - tbits, org);
 #pragma unroll
@@ -502,7 +516,7 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       // DPP latencies better than two interleaved points at three waves
       for (int li = l0; li < l1; ++li) {
         PointVals<D, T> q0;
-        point_basis<D, T, NLEAD>(s_tt, a.ppb, li, hc, q0);
+        point_basis<D, T, NLEAD>(s_tt, a.ppb, sbase + li, hc, q0);
         T s0;
         if constexpr (MODE == kApply) s0 = group_sum<T, L>(q0.w * point_gather<D, T>(q0, cv));
         else if constexpr (MODE == kRhs) s0 = T(a.y[pos + li]);

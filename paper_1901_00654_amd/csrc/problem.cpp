@@ -606,6 +606,18 @@ template void profile_apply<float>(Problem*, int, int, double*, double*);
 // Device scalars: dots go to slots; read back with one synchronising copy.
 double* Problem::slot(int i) { return slots.p + i; }
 
+void Problem::copy_slots(int first, int count) {
+  hip_check(hipMemcpyAsync(host_slots + first, slots.p + first, sizeof(double) * count, hipMemcpyDeviceToHost,
+                           stream),
+            "slot readback");
+  hip_check(hipEventRecord(slots_ready, stream), "record");
+}
+
+void Problem::wait_slots(int first, int count, double* host) {
+  hip_check(hipEventSynchronize(slots_ready), "event sync");
+  std::memcpy(host, host_slots + first, sizeof(double) * count);
+}
+
 void Problem::read_slots(int first, int count, double* host) {
   hip_check(hipMemcpyAsync(host_slots + first, slots.p + first, sizeof(double) * count, hipMemcpyDeviceToHost,
                            stream),
@@ -917,6 +929,7 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
       P->own_stream = true;
     }
     hip_check(hipHostMalloc(reinterpret_cast<void**>(&P->host_slots), sizeof(double) * kSlots), "pinned");
+    hip_check(hipEventCreateWithFlags(&P->slots_ready, hipEventDisableTiming), "event");
     P->slots.alloc(kSlots);
     P->partial.alloc(kMaxPartials);
     P->flag.alloc(1);
@@ -1091,6 +1104,7 @@ Problem::~Problem() {
   if (stream) (void)hipStreamSynchronize(stream);
   lev.clear();
   if (host_slots) (void)hipHostFree(host_slots);
+  if (slots_ready) (void)hipEventDestroy(slots_ready);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 

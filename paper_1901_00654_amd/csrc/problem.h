@@ -146,6 +146,12 @@ struct Problem {
 
   double* slot(int i);
   void read_slots(int first, int count, double* host);
+  // read_slots in two halves: queue the copy (and an event) on the stream,
+  // then wait for that event and read; work queued in between overlaps the
+  // host's wait
+  void copy_slots(int first, int count);
+  void wait_slots(int first, int count, double* host);
+  hipEvent_t slots_ready = nullptr;
   ~Problem();
 };
 

@@ -122,15 +122,19 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
       dot_op<double, double>(P, p, v, K, kPV);
       hip_check(launch_cg_step<double, double>(alpha, r, p, v, K, P->slot(sa), P->slot(kPV), st), "cg step");
       dot_op<double, double>(P, r, r, K, kRR);
+      if (pc32) dot_op<double, double>(P, r, z, K, kRZo);   // r_new' z_old
+      P->copy_slots(kPV, 2);
+      // the next V-cycle is queued before the host reads the residual, so the
+      // device does not idle during the readback; after the last iteration
+      // it is wasted (z is not used again)
+      precondition(P, pc32, r, z, kRR);
       double h[2];
-      P->read_slots(kPV, 2, h);
+      P->wait_slots(kPV, 2, h);
       ++total;
       if (!finite_pos(h[0]) || !std::isfinite(h[1]))
         throw Error{TS_EBREAKDOWN, "CG breakdown: p'Ap = " + std::to_string(h[0])};
       report(every, pc32 ? "vcycle32" : "fp64", total, std::sqrt(h[1]) / bnorm);
       if (std::sqrt(h[1]) / bnorm <= tol) break;
-      if (pc32) dot_op<double, double>(P, r, z, K, kRZo);   // r_new' z_old
-      precondition(P, pc32, r, z, kRR);
       dot_op<double, double>(P, r, z, K, sb);
       if (pc32) hip_check(launch_p_update_flex(p, z, K, P->slot(sb), P->slot(kRZo), P->slot(sa), st), "p update");
       else hip_check(launch_p_update<double>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");

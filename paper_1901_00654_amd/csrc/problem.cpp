@@ -357,7 +357,8 @@ static WorkListHost make_worklist(int D, int G, int g, int tb, int64_t ppb, cons
         uint32_t flags = uint32_t(t);
         if (k0 == s0) flags |= kChunkFirst;
         if (k1 == s1) flags |= kChunkLast;
-        chunks.push_back(make_int4(int(k0), int(k1), int(items.size()), int(flags)));
+        const size_t item0 = items.size();
+        chunks.push_back(make_int4(int(k0), int(k1), int(item0), int(flags)));
         while (j < cells_in_tile && cell_start(c0 + j + 1) <= k0) ++j;
         for (int jj = j; jj < cells_in_tile; ++jj) {
           if (cell_start(c0 + jj) >= k1) break;
@@ -366,6 +367,11 @@ static WorkListHost make_worklist(int D, int G, int g, int tb, int64_t ppb, cons
             items.push_back(uint32_t(jj) | (uint32_t(q - k0) << kItemLoShift) |
                             (uint32_t(std::min<int64_t>(Q, hi - q)) << kItemCntShift));
         }
+        // longest items first: the lane groups of a wave then get items of
+        // similar length, and a wave runs as many steps as its longest item
+        std::stable_sort(items.begin() + int64_t(item0), items.end(), [](uint32_t x, uint32_t y) {
+          return (x >> kItemCntShift) > (y >> kItemCntShift);
+        });
       }
     }
     if (int64_t(items.size()) >= INT32_MAX || int64_t(chunks.size()) >= INT32_MAX)

@@ -1584,11 +1584,26 @@ __device__ __forceinline__ void stencil_out(const T* x, T* out, const T* b, cons
   }
 }
 
+// Flat index offset (>= 0) of stored stencil point h: the base-7 digits of
+// NO/2 + h, each minus 3, weighted by the strides J^(D-1-p).
+template <int D>
+__device__ __forceinline__ int64_t stencil_off(int h, int J) {
+  int o = stencil_half<D>() - 1 + h;
+  int64_t off = 0, stride = 1;
+#pragma unroll
+  for (int p = D - 1; p >= 0; --p) {
+    off += int64_t(o % 7 - 3) * stride;
+    o /= 7;
+    stride *= J;
+  }
+  return off;
+}
+
 // Stored offsets h and their mirrors, for row k.
-template <typename T, int EPI>
-__device__ __forceinline__ void stencil_pair(const T* S, const int32_t* offs, const T* x, const T* b, const T* w,
-                                             int64_t K, int64_t k, int h, T& a0, T& a1) {
-  const int64_t off = offs[h];
+template <typename T, int D, int EPI>
+__device__ __forceinline__ void stencil_pair(const T* S, int J, const T* x, const T* b, const T* w, int64_t K,
+                                             int64_t k, int h, T& a0, T& a1) {
+  const int64_t off = stencil_off<D>(h, J);
   int64_t i = k + off;
   i = i >= K ? K - 1 : i;
   a0 += S[int64_t(h) * K + k] * stencil_in<T, EPI>(x, b, w, i);
@@ -1601,8 +1616,8 @@ __device__ __forceinline__ void stencil_pair(const T* S, const int32_t* offs, co
 // with many rows (streams the stored half once; its mirror reads come back
 // from cache).
 template <typename T, int D, int EPI>
-__global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int32_t* offs, const T* x, T* out,
-                                                          const T* b, const T* w, int64_t K) {
+__global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, int J, const T* x, T* out, const T* b,
+                                                          const T* w, int64_t K) {
   constexpr int NH = stencil_half<D>();
   constexpr int PERG = (NH + 6) / 7;
   __shared__ T part[7][kStRows];
@@ -1614,7 +1629,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int3
     T a0 = T(0), a1 = T(0);
     if (k < K) {
       const int h1 = min(NH, (grp + 1) * PERG);
-      for (int h = grp * PERG; h < h1; ++h) stencil_pair<T, EPI>(S, offs, x, b, w, K, k, h, a0, a1);
+      for (int h = grp * PERG; h < h1; ++h) stencil_pair<T, D, EPI>(S, J, x, b, w, K, k, h, a0, a1);
     }
     part[grp][rl] = a0 + a1;
   }
@@ -1629,17 +1644,19 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply(const T* S, const int3
 
 // The same product for levels with few rows, where the kernel above is
 // latency-bound: 8 rows per block, 32 threads per row, each taking every
-// 32nd stored offset, summed by a tree in LDS.
+// 32nd stored offset; a row's 8 threads in a wave are summed by lane
+// exchanges, the 4 waves in LDS.
 constexpr int kStSmallRows = 8;
 constexpr int kStSmallCols = kBlock / kStSmallRows;
 constexpr int64_t kStSmallMaxK = 16384;
 
 template <typename T, int D, int EPI>
-__global__ __launch_bounds__(kBlock) void k_stencil_apply_small(const T* S, const int32_t* offs, const T* x, T* out,
-                                                                const T* b, const T* w, int64_t K) {
+__global__ __launch_bounds__(kBlock) void k_stencil_apply_small(const T* S, int J, const T* x, T* out, const T* b,
+                                                                const T* w, int64_t K) {
   constexpr int NH = stencil_half<D>();
   constexpr int PER = (NH + kStSmallCols - 1) / kStSmallCols;
-  __shared__ T part[kStSmallCols][kStSmallRows];
+  static_assert(kStSmallRows == 8 && kBlock == 256, "lane layout below");
+  __shared__ T part[kBlock / 64][kStSmallRows];
   const int r = threadIdx.x % kStSmallRows;
   const int c = threadIdx.x / kStSmallRows;
   const int64_t k = int64_t(blockIdx.x) * kStSmallRows + r;
@@ -1648,17 +1665,23 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply_small(const T* S, cons
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int h = c + q * kStSmallCols;
-      if (h < NH) stencil_pair<T, EPI>(S, offs, x, b, w, K, k, h, a0, a1);
+      if (h < NH) stencil_pair<T, D, EPI>(S, J, x, b, w, K, k, h, a0, a1);
     }
   }
-  part[c][r] = a0 + a1;
+  // lanes r, r + 8, ..., r + 56 of a wave hold row r
+  T a = a0 + a1;
+  a += __shfl_xor(a, 8);
+  a += __shfl_xor(a, 16);
+  a += __shfl_xor(a, 32);
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  if (lane < kStSmallRows) part[wv][lane] = a;
   __syncthreads();
+  if (threadIdx.x < kStSmallRows && k < K) {
+    T v = part[0][r];
 #pragma unroll
-  for (int h = kStSmallCols / 2; h >= 1; h >>= 1) {
-    if (c < h) part[c][r] += part[c + h][r];
-    __syncthreads();
+    for (int q = 1; q < kBlock / 64; ++q) v += part[q][r];
+    stencil_out<T, EPI>(x, out, b, w, k, v);
   }
-  if (c == 0 && k < K) stencil_out<T, EPI>(x, out, b, w, k, part[0][r]);
 }
 
 // ---------------------------------------------------------------------------
@@ -2081,45 +2104,45 @@ hipError_t launch_stencil_finalize(int D, const double* inter, const double* ban
 }
 
 template <typename T, int EPI>
-static hipError_t launch_stencil_epi(int D, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
-                                     const T* w, int64_t K, hipStream_t st) {
+static hipError_t launch_stencil_epi(int D, const T* S, int J, const T* x, T* out, const T* b, const T* w,
+                                     int64_t K, hipStream_t st) {
   if (K <= kStSmallMaxK) {
     const unsigned gs = unsigned((K + kStSmallRows - 1) / kStSmallRows);
     switch (D) {
-      case 1: hipLaunchKernelGGL((k_stencil_apply_small<T, 1, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-      case 2: hipLaunchKernelGGL((k_stencil_apply_small<T, 2, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-      case 3: hipLaunchKernelGGL((k_stencil_apply_small<T, 3, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-      case 4: hipLaunchKernelGGL((k_stencil_apply_small<T, 4, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-      case 5: hipLaunchKernelGGL((k_stencil_apply_small<T, 5, EPI>), dim3(gs), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+      case 1: hipLaunchKernelGGL((k_stencil_apply_small<T, 1, EPI>), dim3(gs), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+      case 2: hipLaunchKernelGGL((k_stencil_apply_small<T, 2, EPI>), dim3(gs), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+      case 3: hipLaunchKernelGGL((k_stencil_apply_small<T, 3, EPI>), dim3(gs), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+      case 4: hipLaunchKernelGGL((k_stencil_apply_small<T, 4, EPI>), dim3(gs), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+      case 5: hipLaunchKernelGGL((k_stencil_apply_small<T, 5, EPI>), dim3(gs), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
   }
   const unsigned g = unsigned((K + kStRows - 1) / kStRows);
   switch (D) {
-    case 1: hipLaunchKernelGGL((k_stencil_apply<T, 1, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-    case 2: hipLaunchKernelGGL((k_stencil_apply<T, 2, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-    case 3: hipLaunchKernelGGL((k_stencil_apply<T, 3, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-    case 4: hipLaunchKernelGGL((k_stencil_apply<T, 4, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
-    case 5: hipLaunchKernelGGL((k_stencil_apply<T, 5, EPI>), dim3(g), dim3(kBlock), 0, st, S, offs, x, out, b, w, K); break;
+    case 1: hipLaunchKernelGGL((k_stencil_apply<T, 1, EPI>), dim3(g), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+    case 2: hipLaunchKernelGGL((k_stencil_apply<T, 2, EPI>), dim3(g), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+    case 3: hipLaunchKernelGGL((k_stencil_apply<T, 3, EPI>), dim3(g), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+    case 4: hipLaunchKernelGGL((k_stencil_apply<T, 4, EPI>), dim3(g), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
+    case 5: hipLaunchKernelGGL((k_stencil_apply<T, 5, EPI>), dim3(g), dim3(kBlock), 0, st, S, J, x, out, b, w, K); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_stencil_apply(int D, int epi, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
-                                const T* w, int64_t K, hipStream_t st) {
+hipError_t launch_stencil_apply(int D, int epi, const T* S, int J, const T* x, T* out, const T* b, const T* w,
+                                int64_t K, hipStream_t st) {
   if (K == 0) return hipSuccess;
-  if (epi == kStPlain) return launch_stencil_epi<T, kStPlain>(D, S, offs, x, out, b, w, K, st);
-  if (epi == kStJacobi) return launch_stencil_epi<T, kStJacobi>(D, S, offs, x, out, b, w, K, st);
-  if (epi == kStResidual) return launch_stencil_epi<T, kStResidual>(D, S, offs, x, out, b, w, K, st);
-  if (epi == kStJacobiZero) return launch_stencil_epi<T, kStJacobiZero>(D, S, offs, x, out, b, w, K, st);
+  if (epi == kStPlain) return launch_stencil_epi<T, kStPlain>(D, S, J, x, out, b, w, K, st);
+  if (epi == kStJacobi) return launch_stencil_epi<T, kStJacobi>(D, S, J, x, out, b, w, K, st);
+  if (epi == kStResidual) return launch_stencil_epi<T, kStResidual>(D, S, J, x, out, b, w, K, st);
+  if (epi == kStJacobiZero) return launch_stencil_epi<T, kStJacobiZero>(D, S, J, x, out, b, w, K, st);
   return hipErrorInvalidValue;
 }
-template hipError_t launch_stencil_apply<double>(int, int, const double*, const int32_t*, const double*, double*,
+template hipError_t launch_stencil_apply<double>(int, int, const double*, int, const double*, double*,
                                                  const double*, const double*, int64_t, hipStream_t);
-template hipError_t launch_stencil_apply<float>(int, int, const float*, const int32_t*, const float*, float*,
-                                                const float*, const float*, int64_t, hipStream_t);
+template hipError_t launch_stencil_apply<float>(int, int, const float*, int, const float*, float*, const float*,
+                                                const float*, int64_t, hipStream_t);
 
 }  // namespace tsmg

@@ -114,8 +114,8 @@ hipError_t launch_stencil_finalize(int D, const double* inter, const double* ban
 // from zero, out = x1 + w (b - A x1) with x1 = w b (x unused). out must not
 // alias x, b or w.
 template <typename T>
-hipError_t launch_stencil_apply(int D, int epi, const T* S, const int32_t* offs, const T* x, T* out, const T* b,
-                                const T* w, int64_t K, hipStream_t st);
+hipError_t launch_stencil_apply(int D, int epi, const T* S, int J, const T* x, T* out, const T* b, const T* w,
+                                int64_t K, hipStream_t st);
 
 // Radix sort of (key, index) pairs on the low `bits` bits (sort.hip).
 hipError_t sort_pairs(uint32_t* key_in, uint32_t* key_out, uint32_t* val_in, uint32_t* val_out, int64_t n,

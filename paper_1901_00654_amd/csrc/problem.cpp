@@ -412,7 +412,7 @@ template <typename T>
 void apply_op(Problem* P, int g, const T* c, T* out) {
   Level& L = P->lev[g];
   if (L.stencil) {
-    hip_check(launch_stencil_apply<T>(P->d, 0, lvl_S<T>(L), L.soffs.p, c, out, nullptr, nullptr, L.K, P->stream),
+    hip_check(launch_stencil_apply<T>(P->d, 0, lvl_S<T>(L), L.J, c, out, nullptr, nullptr, L.K, P->stream),
               "stencil apply");
     P->applies++;
     return;
@@ -526,10 +526,10 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
     T* cur = (swaps % 2 == 0) ? alpha : t;
     T* oth = (cur == alpha) ? t : alpha;
     if (nu1 >= 2) {
-      hip_check(launch_stencil_apply<T>(P->d, 3, S, L.soffs.p, nullptr, cur, b, w, K, P->stream), "jacobi");
+      hip_check(launch_stencil_apply<T>(P->d, 3, S, L.J, nullptr, cur, b, w, K, P->stream), "jacobi");
       P->applies++;
       for (int j = 2; j < nu1; ++j) {
-        hip_check(launch_stencil_apply<T>(P->d, 1, S, L.soffs.p, cur, oth, b, w, K, P->stream), "jacobi");
+        hip_check(launch_stencil_apply<T>(P->d, 1, S, L.J, cur, oth, b, w, K, P->stream), "jacobi");
         P->applies++;
         std::swap(cur, oth);
       }
@@ -538,13 +538,13 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
     } else {
       hip_check(launch_fill<T>(cur, T(0), K, P->stream), "fill");
     }
-    hip_check(launch_stencil_apply<T>(P->d, 2, S, L.soffs.p, cur, oth, b, w, K, P->stream), "residual");
+    hip_check(launch_stencil_apply<T>(P->d, 2, S, L.J, cur, oth, b, w, K, P->stream), "residual");
     P->applies++;
     restrict_op<T>(P, g, oth, lvl_b<T>(C), static_cast<const T*>(nullptr));
     vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
     prolong_op<T>(P, g, lvl_a<T>(C), cur, true);
     for (int j = 0; j < nu2; ++j) {
-      hip_check(launch_stencil_apply<T>(P->d, 1, S, L.soffs.p, cur, oth, b, w, K, P->stream), "jacobi");
+      hip_check(launch_stencil_apply<T>(P->d, 1, S, L.J, cur, oth, b, w, K, P->stream), "jacobi");
       P->applies++;
       std::swap(cur, oth);
     }
@@ -758,19 +758,6 @@ static void build_stencil(Problem* P, int g, DevBuf<double>& mom, bool want_coar
   L.S64.alloc(size_t(NH * L.K));
   L.S32.alloc(size_t(NH * L.K));
   hip_check(launch_stencil_finalize(D, cur, L.band64.p, J, L.K, P->lam, L.S64.p, L.S32.p, P->stream), "finalize");
-  std::vector<int32_t> offs(static_cast<size_t>(NH));   // flat offsets (>= 0) of the stored half
-  for (int64_t h = 0; h < NH; ++h) {
-    int64_t rem = NO / 2 + h, off = 0, stride = 1;
-    for (int p = D - 1; p >= 0; --p) {
-      off += (rem % 7 - 3) * stride;
-      rem /= 7;
-      stride *= J;
-    }
-    offs[size_t(h)] = int32_t(off);
-  }
-  L.soffs.alloc(offs.size());
-  hip_check(hipMemcpyAsync(L.soffs.p, offs.data(), offs.size() * sizeof(int32_t), hipMemcpyHostToDevice, P->stream),
-            "upload");
   hip_check(hipStreamSynchronize(P->stream), "sync");   // temporaries and host tables go out of scope
   mom = std::move(coarser);
   L.stencil = true;
@@ -824,7 +811,7 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
     }
     // level 1 always carries its stencil: A_1 is expanded from it
     if (g == 1 || st) {
-      stencils += (ipow(7, d) + 1) / 2 * (K * 12 + 4);   // the stored half
+      stencils += (ipow(7, d) + 1) / 2 * K * 12;   // the stored half, FP64 + FP32
       // two pass buffers, plus the moments handed on to level g-1
       const int64_t coarser = g > 1 ? ipow(7 * int64_t(1 << (g - 1)), d) * 8 : 0;
       stencil_tmp = std::max(stencil_tmp, 2 * ipow(7 * int64_t(J), d) * 8 + coarser + (1 << 16));

@@ -91,7 +91,6 @@ struct Level {
   bool stencil = false;            // A_g assembled as a 7^d-point stencil
   DevBuf<double> S64;              // [(7^d+1)/2][K] offset-major stencil, upper half of the offsets
   DevBuf<float> S32;
-  DevBuf<int32_t> soffs;           // [(7^d+1)/2] flat index offset (>= 0) of each stored stencil point
   // work list of the point pass (levels applied matrix-free)
   DevBuf<int32_t> wl_first;        // [workgroups + 1]
   DevBuf<int4> wl_chunks;          // [chunks + 1]

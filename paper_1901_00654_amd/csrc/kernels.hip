@@ -602,21 +602,25 @@ __global__ __launch_bounds__(kBlock) void k_lambda_pass(LambdaArgs<T> a) {
 // (out-of-grid entries of c are zero, which drops the same taps the pass form
 // skips). band: d blocks of [3][J][7] (M, G1, G2 per dimension).
 //
-// d = 3: a workgroup owns a kLamT x kLamT column tile in dimensions 1 and 2
-// (halo included, so kLamB = kLamT - 6 outputs per edge) and a run of kLamC0
-// output planes along dimension 0. Each thread loads its column of c over the
-// run and its halo into registers once; then, kLamP planes at a time, the
-// dimension-0 contraction happens in registers and the dimension-1 and
-// dimension-2 passes go through LDS (two barriers per kLamP planes; the
-// planes of a step are independent, which hides LDS latency). Every c entry
-// is read (kLamT / kLamB)^2 (kLamC0 + 6) / kLamC0 times, from L2 mostly.
+// Last three dimensions (all three at d = 3; at d >= 4 after k_lambda_pass
+// has run the leading ones, which leaves three tensors T0, T1, T2): a
+// workgroup owns a kLamT x kLamT column tile in the last two dimensions
+// (halo included, so kLamB = kLamT - 6 outputs per edge), a run of C0 output
+// planes along the third-to-last dimension and one index of the leading
+// dimensions (`outer`, each a J^3 block). Each thread loads its column of
+// the input(s) over the run and its halo into registers once; then, kLamP
+// planes at a time, the first contraction happens in registers and the
+// other two go through LDS (two barriers per kLamP planes; the planes of a
+// step are independent, which hides LDS latency). Every input entry is read
+// (kLamT / kLamB)^2 (C0 + 6) / C0 times, from L2 mostly.
 constexpr int kLamT = 16;
 constexpr int kLamB = kLamT - 6;
-constexpr int kLamC0 = 8;
+constexpr int kLamC0 = 8;    // planes per run, one input tensor (d = 3)
+constexpr int kLamC0x3 = 4;  // planes per run, three input tensors (d >= 4)
 constexpr int kLamP = 2;
-constexpr int kLamS = kLamT + 1;   // LDS row stride after dimension 1 (odd: rows fall on different banks)
+constexpr int kLamS = kLamT + 1;   // LDS row stride after the second dimension (odd: rows fall on different banks)
 static_assert(kLamT * kLamT == kBlock, "one thread per column of the tile");
-static_assert(kLamC0 % kLamP == 0, "whole steps per run");
+static_assert(kLamC0 % kLamP == 0 && kLamC0x3 % kLamP == 0, "whole steps per run");
 
 template <typename T>
 __device__ __forceinline__ void band_row(const T* band, int J, int j, T (&m)[7], T (&g1)[7], T (&g2)[7]) {
@@ -628,30 +632,41 @@ __device__ __forceinline__ void band_row(const T* band, int J, int j, T (&m)[7],
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* __restrict__ c, T* __restrict__ out,
-                                                          const T* __restrict__ band, int J, int B, int nt, T lam) {
-  __shared__ T s1[kLamP][3][kLamT * kLamT];   // T0, T1, T2 after dimension 0, per column
-  __shared__ T s2[kLamP][3][kLamB * kLamS];   // after dimension 1
-  __shared__ T sb[3][kLamC0][7];              // dimension-0 band rows (M, G1, G2) of the run
+// c0, c1, c2: the input tensors (c1, c2 read only when THREE); band: the
+// factors of the last three dimensions, [3][3][J][7].
+template <typename T, bool THREE, int C0>
+__global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* __restrict__ c0, const T* __restrict__ c1,
+                                                          const T* __restrict__ c2, T* __restrict__ out,
+                                                          const T* __restrict__ band, int J, int B, int nt, int nt0,
+                                                          T lam) {
+  __shared__ T s1[kLamP][3][kLamT * kLamT];   // T0, T1, T2 after the first dimension, per column
+  __shared__ T s2[kLamP][3][kLamB * kLamS];   // after the second
+  __shared__ T sb[3][C0][7];                  // first-dimension band rows (M, G1, G2) of the run
   const int wg = xcd_block();   // an XCD takes whole runs of planes: the halos stay in its L2
   const int t2 = wg % nt;
   const int t1 = (wg / nt) % nt;
-  const int z0 = (wg / (nt * nt)) * kLamC0;
+  const int z0 = ((wg / (nt * nt)) % nt0) * C0;
   const int64_t JJ = int64_t(J) * J;
+  const int64_t base = int64_t(wg / (nt * nt * nt0)) * JJ * J;   // the outer block
   const int tid = threadIdx.x;
-  T v[kLamC0 + 6];
+  T v0[C0 + 6], v1[THREE ? C0 + 6 : 1], v2[THREE ? C0 + 6 : 1];
   {
     const int g1 = t1 * B - 3 + tid / kLamT, g2 = t2 * B - 3 + tid % kLamT;
     const bool col = g1 >= 0 && g1 < J && g2 >= 0 && g2 < J;
 #pragma unroll
-    for (int i = 0; i < kLamC0 + 6; ++i) {
+    for (int i = 0; i < C0 + 6; ++i) {
       const int g0 = z0 - 3 + i;
-      v[i] = (col && g0 >= 0 && g0 < J) ? c[int64_t(g0) * JJ + int64_t(g1) * J + g2] : T(0);
+      const bool ok = col && g0 >= 0 && g0 < J;
+      const int64_t idx = base + int64_t(g0) * JJ + int64_t(g1) * J + g2;
+      v0[i] = ok ? c0[idx] : T(0);
+      if constexpr (THREE) {
+        v1[i] = ok ? c1[idx] : T(0);
+        v2[i] = ok ? c2[idx] : T(0);
+      }
     }
   }
-  // dimension-1 pass: thread -> (row b1a of the output tile, column h2a);
-  // dimension-2 pass: thread -> output (b1b, b2b)
+  // second dimension: thread -> (row b1a of the output tile, column h2a);
+  // third: thread -> output (b1b, b2b)
   const int b1a = tid / kLamT, h2a = tid % kLamT;
   const int b1b = tid / B, b2b = tid % B;
   const bool do1 = b1a < B && t1 * B + b1a < J;
@@ -659,23 +674,30 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* __restrict__ 
   T m1[7], p1[7], q1[7], m2[7], p2[7], q2[7];
   band_row(band + size_t(3) * J * 7, J, do1 ? t1 * B + b1a : 0, m1, p1, q1);
   band_row(band + size_t(6) * J * 7, J, do2 ? t2 * B + b2b : 0, m2, p2, q2);
-  const int nsteps = min(kLamC0, J - z0);
-  for (int e = tid; e < 3 * kLamC0 * 7; e += kBlock) {
-    const int kind = e / (kLamC0 * 7), i = (e / 7) % kLamC0, o = e % 7;
+  const int nsteps = min(C0, J - z0);
+  for (int e = tid; e < 3 * C0 * 7; e += kBlock) {
+    const int kind = e / (C0 * 7), i = (e / 7) % C0, o = e % 7;
     sb[kind][i][o] = i < nsteps ? band[(size_t(kind) * J + z0 + i) * 7 + o] : T(0);
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < kLamC0; i += kLamP) {
+  for (int i = 0; i < C0; i += kLamP) {
     if (i >= nsteps) break;
 #pragma unroll
     for (int p = 0; p < kLamP; ++p) {
       T a0 = T(0), a1 = T(0), a2 = T(0);
 #pragma unroll
       for (int o = 0; o < 7; ++o) {
-        a0 += sb[0][i + p][o] * v[i + p + o];
-        a1 += sb[1][i + p][o] * v[i + p + o];
-        a2 += sb[2][i + p][o] * v[i + p + o];
+        const T m = sb[0][i + p][o], g1 = sb[1][i + p][o], g2 = sb[2][i + p][o];
+        if constexpr (THREE) {
+          a0 += m * v0[i + p + o];
+          a1 += m * v1[i + p + o] + g1 * v0[i + p + o];
+          a2 += m * v2[i + p + o] + g2 * v0[i + p + o] + T(2) * g1 * v1[i + p + o];
+        } else {
+          a0 += m * v0[i + p + o];
+          a1 += g1 * v0[i + p + o];
+          a2 += g2 * v0[i + p + o];
+        }
       }
       s1[p][0][tid] = a0;
       s1[p][1][tid] = a1;
@@ -689,11 +711,11 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* __restrict__ 
 #pragma unroll
         for (int o = 0; o < 7; ++o) {
           const int q = (b1a + o) * kLamT + h2a;
-          const T v0 = s1[p][0][q], v1 = s1[p][1][q], v2 = s1[p][2][q];
-          a0 += m1[o] * v0;
-          a1 += m1[o] * v1 + p1[o] * v0;
-          a2 += m1[o] * v2 + q1[o] * v0;
-          a3 += p1[o] * v1;
+          const T w0 = s1[p][0][q], w1 = s1[p][1][q], w2 = s1[p][2][q];
+          a0 += m1[o] * w0;
+          a1 += m1[o] * w1 + p1[o] * w0;
+          a2 += m1[o] * w2 + q1[o] * w0;
+          a3 += p1[o] * w1;
         }
         s2[p][0][b1a * kLamS + h2a] = a0;
         s2[p][1][b1a * kLamS + h2a] = a1;
@@ -712,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_lambda_fused3(const T* __restrict__ 
           a += m2[o] * s2[p][2][q] + q2[o] * s2[p][0][q];
           b += p2[o] * s2[p][1][q];
         }
-        out[int64_t(z0 + i + p) * JJ + int64_t(t1 * B + b1b) * J + (t2 * B + b2b)] = lam * (a + T(2) * b);
+        out[base + int64_t(z0 + i + p) * JJ + int64_t(t1 * B + b1b) * J + (t2 * B + b2b)] = lam * (a + T(2) * b);
       }
     }
   }
@@ -1753,8 +1775,8 @@ hipError_t launch_lambda_fused(int D, const T* c, T* out, const T* band, int J, 
   if (D == 3) {
     const int nt = (J + kLamB - 1) / kLamB, B = (J + nt - 1) / nt;   // B <= kLamB
     const int nt0 = (J + kLamC0 - 1) / kLamC0;
-    hipLaunchKernelGGL(k_lambda_fused3<T>, dim3(unsigned(nt0 * nt * nt)), dim3(kBlock), 0, st, c, out, band, J, B, nt,
-                       lam);
+    hipLaunchKernelGGL((k_lambda_fused3<T, false, kLamC0>), dim3(unsigned(nt0 * nt * nt)), dim3(kBlock), 0, st, c,
+                       nullptr, nullptr, out, band, J, B, nt, nt0, lam);
     return hipGetLastError();
   }
   if (D == 2) {
@@ -1766,6 +1788,22 @@ hipError_t launch_lambda_fused(int D, const T* c, T* out, const T* band, int J, 
   }
   return hipErrorInvalidValue;
 }
+template <typename T>
+hipError_t launch_lambda_tail3(const T* t0, const T* t1, const T* t2, T* out, const T* band, int J, int64_t outer,
+                               T lam, hipStream_t st) {
+  const int nt = (J + kLamB - 1) / kLamB, B = (J + nt - 1) / nt;
+  const int nt0 = (J + kLamC0x3 - 1) / kLamC0x3;
+  const int64_t blocks = outer * nt0 * nt * nt;
+  if (blocks == 0) return hipSuccess;
+  if (blocks > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_lambda_fused3<T, true, kLamC0x3>), dim3(unsigned(blocks)), dim3(kBlock), 0, st, t0, t1, t2,
+                     out, band, J, B, nt, nt0, lam);
+  return hipGetLastError();
+}
+template hipError_t launch_lambda_tail3<double>(const double*, const double*, const double*, double*, const double*,
+                                                int, int64_t, double, hipStream_t);
+template hipError_t launch_lambda_tail3<float>(const float*, const float*, const float*, float*, const float*, int,
+                                               int64_t, float, hipStream_t);
 template hipError_t launch_lambda_fused<double>(int, const double*, double*, const double*, int, double, hipStream_t);
 template hipError_t launch_lambda_fused<float>(int, const float*, float*, const float*, int, float, hipStream_t);
 

@@ -43,6 +43,12 @@ template <typename T> hipError_t launch_lambda_pass(const LambdaArgs<T>& a, hipS
 // out = lam * Lambda c in one kernel (d = 2 or 3); band: d blocks of [3][J][7].
 template <typename T>
 hipError_t launch_lambda_fused(int D, const T* c, T* out, const T* band, int J, T lam, hipStream_t st);
+// out = lam * (the last three dimensions of the recursion) applied to
+// (t0, t1, t2) for each of `outer` leading blocks of J^3 entries; band: the
+// factors of those three dimensions, [3][3][J][7].
+template <typename T>
+hipError_t launch_lambda_tail3(const T* t0, const T* t1, const T* t2, T* out, const T* band, int J, int64_t outer,
+                               T lam, hipStream_t st);
 hipError_t launch_lambda_diag(int D, const double* band, int J, int64_t K, double lam, double* out,
                               hipStream_t st);
 template <typename T> hipError_t launch_transfer(bool prolong, const TransferArgs<T>& a, hipStream_t st);

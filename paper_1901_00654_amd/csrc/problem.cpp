@@ -246,7 +246,9 @@ template <typename T> static T* prob_xfer(Problem* P);
 template <> double* prob_xfer<double>(Problem* P) { return P->xfer64.p; }
 template <> float* prob_xfer<float>(Problem* P) { return P->xfer32.p; }
 
-// out = lambda Lambda_g c: D banded passes (the three-accumulator recursion).
+// out = lambda Lambda_g c by the three-accumulator recursion (Alg. 2): one
+// kernel for d = 2, 3; for d >= 4 banded passes over the leading d - 3
+// dimensions, then one kernel for the last three; one banded pass for d = 1.
 template <typename T>
 static void lambda_apply(Problem* P, int g, const T* c, T* out) {
   Level& L = P->lev[g];
@@ -263,6 +265,26 @@ static void lambda_apply(Problem* P, int g, const T* c, T* out) {
   const T* in1 = nullptr;
   const T* in2 = nullptr;
   int64_t stride = K;
+  if (D >= 4) {
+    for (int p = 0; p < D - 3; ++p) {
+      stride /= L.J;
+      LambdaArgs<T> a{};
+      a.in0 = in0; a.in1 = in1; a.in2 = in2;
+      a.band = lvl_band<T>(L) + size_t(p) * 3 * L.J * 7;
+      a.K = K; a.stride = stride; a.J = L.J;
+      a.first = (p == 0); a.last = false;
+      a.lam = T(P->lam);
+      T* o = (p % 2 == 0) ? bufA : bufB;
+      a.out0 = o; a.out1 = o + K; a.out2 = o + 2 * K;
+      a.out = out;
+      hip_check(launch_lambda_pass<T>(a, P->stream), "lambda pass");
+      in0 = a.out0; in1 = a.out1; in2 = a.out2;
+    }
+    hip_check(launch_lambda_tail3<T>(in0, in1, in2, out, lvl_band<T>(L) + size_t(D - 3) * 3 * L.J * 7, L.J,
+                                     K / (int64_t(L.J) * L.J * L.J), T(P->lam), P->stream),
+              "lambda");
+    return;
+  }
   for (int p = 0; p < D; ++p) {
     stride /= L.J;
     LambdaArgs<T> a{};

@@ -65,13 +65,14 @@ def test_apply_every_level_matrix_free_and_stencil(prob, mode):
         S.close()
 
 
-@pytest.mark.parametrize("N", [16, 32])
-def test_apply_lambda_dominated_d3(lib, N):
-    """lambda so large that lambda*Lambda dominates A_g (d = 3): the fused
-    Lambda kernel's column tiles, halos and runs of planes (J = 19 and 35
-    span several of each, with ragged last ones) against the oracle on every
-    level, FP64 and FP32."""
-    w = gc.uniform_case(3, 3001, N, 1e3, 7)
+@pytest.mark.parametrize("d,N", [(3, 16), (3, 32), (4, 16), (5, 8)])
+def test_apply_lambda_dominated(lib, d, N):
+    """lambda so large that lambda*Lambda dominates A_g: the fused Lambda
+    kernel's column tiles, halos and runs of planes (J = 11, 19 and 35 span
+    several of each, with ragged last ones), at d >= 4 after the banded
+    passes over the leading dimensions, against the oracle on every level,
+    FP64 and FP32."""
+    w = gc.uniform_case(d, 3001 if d == 3 else 2003, N, 1e3, 7 if d == 3 else 8 + d)
     S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"], stencil_mode=tsmg.TS_STENCIL_NONE)
     try:
         rng = np.random.default_rng(106)

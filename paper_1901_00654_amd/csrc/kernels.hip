@@ -2,23 +2,26 @@
 //
 // Hot path (per operator apply A_g c, Sec. 2.4 / Alg. 2-4 of arXiv:1901.00654):
 //   k_lambda_fused2/3, k_lambda_pass
-//                  out  = lambda Lambda_g c (one LDS-tiled kernel for d = 2, 3,
-//                  one banded pass per dimension otherwise)
+//                  out  = lambda Lambda_g c (one kernel for d = 2, 3; for
+//                  d >= 4 one banded pass per leading dimension, then the
+//                  d = 3 kernel over the last three dimensions)
 //   k_data<kApply> out += Phi_g'(Phi_g c), points sorted by knot cell,
-//                  segments and items from a precomputed work list,
+//                  segments and items from a work list built on the host,
 //                  coefficient patch of a cell tile staged in LDS, per-point
 //                  tensor basis as products of 1D cubic values in registers,
 //                  scatter reduced in LDS before one atomic per patch entry.
 //   k_stencil_apply(_small)
-//                  out = A_g x on levels assembled as 7^d-point stencils,
-//                  with Jacobi / residual epilogues.
+//                  out = A_g x on levels assembled as 7^d-point stencils
+//                  (half stored, A_g being symmetric), with Jacobi /
+//                  residual epilogues.
 // V-cycle pieces: Jacobi kernels (Alg. 6), subdivision prolongation and
 // restriction, pass by pass or fused (Sec. 3.2.3), coarse GEMV with the
 // precomputed inverse (Sec. 3.2.4); CG vector kernels with device-resident
 // scalars (Alg. 8).
-// Setup: binning, offsets, work lists, Jacobi diagonal (Alg. 5 + Kronecker
-// diagonal), stencil assembly from per-cell polynomial moments, Gauss-Jordan
-// inversion of A_1.
+// Setup: binning, offsets, Jacobi diagonal (Alg. 5 + Kronecker diagonal),
+// stencil assembly from per-cell polynomial moments (read from the points
+// on the finest assembled level, carried to coarser ones by a change of
+// variables), Gauss-Jordan inversion of A_1.
 #include <algorithm>
 
 #include "common.h"

@@ -1110,19 +1110,23 @@ __global__ __launch_bounds__(kBlock) void k_axpy_conv(const TI* x, TO* y, int64_
   y[k] = TO(double(y[k]) + s * double(x[k]));
 }
 
-// Lanczos pieces: y = d .* x ; w = d .* x - beta_prev v_prev (beta from slot).
+// Lanczos pieces with device-resident scalars: y = d .* x;
+// w = d .* (A y) - beta v_prev with beta = sqrt(*b2prev) (0 without b2prev);
+// y += (scale * (*s)) x.
 __global__ __launch_bounds__(kBlock) void k_mul(const double* d, const double* x, double* y, int64_t K) {
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (k < K) y[k] = d[k] * x[k];
 }
 __global__ __launch_bounds__(kBlock) void k_lanczos_w(const double* d, const double* Ax, const double* vprev,
-                                                      double beta_prev, double* w, int64_t K) {
+                                                      const double* b2prev, double* w, int64_t K) {
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (k < K) w[k] = d[k] * Ax[k] - beta_prev * vprev[k];
+  if (k >= K) return;
+  const double beta = b2prev ? sqrt(*b2prev) : 0.0;
+  w[k] = d[k] * Ax[k] - beta * vprev[k];
 }
-__global__ __launch_bounds__(kBlock) void k_axpy(double a, const double* x, double* y, int64_t K) {
+__global__ __launch_bounds__(kBlock) void k_axpy(double scale, const double* s, const double* x, double* y, int64_t K) {
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (k < K) y[k] += a * x[k];
+  if (k < K) y[k] += (scale * *s) * x[k];
 }
 __global__ __launch_bounds__(kBlock) void k_start_vector(double* u, int64_t K) {
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -1964,13 +1968,13 @@ hipError_t launch_mul(const double* d, const double* x, double* y, int64_t K, hi
   hipLaunchKernelGGL(k_mul, dim3(blocks_for(K)), dim3(kBlock), 0, st, d, x, y, K);
   return hipGetLastError();
 }
-hipError_t launch_lanczos_w(const double* d, const double* Ax, const double* vprev, double beta_prev, double* w,
+hipError_t launch_lanczos_w(const double* d, const double* Ax, const double* vprev, const double* b2prev, double* w,
                             int64_t K, hipStream_t st) {
-  hipLaunchKernelGGL(k_lanczos_w, dim3(blocks_for(K)), dim3(kBlock), 0, st, d, Ax, vprev, beta_prev, w, K);
+  hipLaunchKernelGGL(k_lanczos_w, dim3(blocks_for(K)), dim3(kBlock), 0, st, d, Ax, vprev, b2prev, w, K);
   return hipGetLastError();
 }
-hipError_t launch_axpy(double a, const double* x, double* y, int64_t K, hipStream_t st) {
-  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(K)), dim3(kBlock), 0, st, a, x, y, K);
+hipError_t launch_axpy(double scale, const double* s, const double* x, double* y, int64_t K, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(blocks_for(K)), dim3(kBlock), 0, st, scale, s, x, y, K);
   return hipGetLastError();
 }
 hipError_t launch_start_vector(double* u, int64_t K, hipStream_t st) {

@@ -82,9 +82,11 @@ template <typename TI, typename TO>
 hipError_t launch_axpy_conv(const TI* x, TO* y, int64_t K, double scale, const double* smul, hipStream_t st);
 
 hipError_t launch_mul(const double* d, const double* x, double* y, int64_t K, hipStream_t st);
-hipError_t launch_lanczos_w(const double* d, const double* Ax, const double* vprev, double beta_prev, double* w,
+// w = d .* Ax - sqrt(*b2prev) vprev (b2prev NULL: no vprev term)
+hipError_t launch_lanczos_w(const double* d, const double* Ax, const double* vprev, const double* b2prev, double* w,
                             int64_t K, hipStream_t st);
-hipError_t launch_axpy(double a, const double* x, double* y, int64_t K, hipStream_t st);
+// y += (scale * *s) x, s on the device
+hipError_t launch_axpy(double scale, const double* s, const double* x, double* y, int64_t K, hipStream_t st);
 hipError_t launch_start_vector(double* u, int64_t K, hipStream_t st);
 hipError_t launch_rsqrt_vec(const double* D, double* out, int64_t K, hipStream_t st);
 hipError_t launch_wdinv(const double* D, double omega, double* w64, float* w32, int64_t K, hipStream_t st);

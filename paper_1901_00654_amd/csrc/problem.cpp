@@ -672,6 +672,9 @@ static void compute_diag(Problem* P, int g) {
 
 // theta_g: largest Ritz value of `steps` Lanczos steps on D^-1/2 A_g D^-1/2
 // from the fixed start u[k] = frac(k * 2654435761 / 2^32) - 1/2.
+// The Lanczos scalars stay on the device (each step's kernels read the
+// previous ones from slots); the host reads them once per batch of steps and
+// applies the early stop afterwards (steps past it are discarded).
 static double lanczos_theta(Problem* P, int g, int steps) {
   Level& L = P->lev[g];
   const int64_t K = L.K;
@@ -681,34 +684,40 @@ static double lanczos_theta(Problem* P, int g, int steps) {
   double* w = P->vp.p;
   double* y = P->vv.p;
   double* Ay = L.t64.p;
+  constexpr int kBatch = (kSlots - kLanczosSlot0 - 1) / 2;
   hip_check(launch_rsqrt_vec(L.diag.p, dis, K, P->stream), "rsqrt");
   hip_check(launch_start_vector(w, K, P->stream), "start");
-  dot_op<double, double>(P, w, w, K, 0);
-  double nrm2;
-  P->read_slots(0, 1, &nrm2);
-  hip_check(launch_scale_copy<double, double>(w, v, K, 1.0 / std::sqrt(nrm2), nullptr, P->stream), "scale");
+  dot_op<double, double>(P, w, w, K, kLanczosSlot0);
+  hip_check(launch_scale_copy<double, double>(w, v, K, 1.0, P->slot(kLanczosSlot0), P->stream), "scale");
   hip_check(launch_fill<double>(vprev, 0.0, K, P->stream), "fill");
-  std::vector<double> al, be;
-  double beta_prev = 0.0;
+  std::vector<double> al, be, h(size_t(2) * kBatch);
   const int m = int(std::min<int64_t>(steps, K));
-  for (int j = 0; j < m; ++j) {
-    hip_check(launch_mul(dis, v, y, K, P->stream), "mul");
-    apply_op<double>(P, g, y, Ay);
-    hip_check(launch_lanczos_w(dis, Ay, vprev, beta_prev, w, K, P->stream), "lanczos");
-    dot_op<double, double>(P, w, v, K, 0);
-    double a;
-    P->read_slots(0, 1, &a);
-    hip_check(launch_axpy(-a, v, w, K, P->stream), "axpy");
-    dot_op<double, double>(P, w, w, K, 0);
-    double b2;
-    P->read_slots(0, 1, &b2);
-    al.push_back(a);
-    const double b = std::sqrt(b2);
-    if (j == m - 1 || b <= 1e-12 * std::fabs(a)) break;
-    be.push_back(b);
-    std::swap(vprev, v);   // vprev <- v
-    hip_check(launch_scale_copy<double, double>(w, v, K, 1.0 / b, nullptr, P->stream), "scale");
-    beta_prev = b;
+  const double* b2prev = nullptr;
+  bool done = false;
+  for (int j = 0; j < m && !done;) {
+    const int nb = std::min(kBatch, m - j);
+    for (int i = 0; i < nb; ++i) {
+      const int sa = kLanczosSlot0 + 1 + 2 * i, sb = sa + 1;
+      hip_check(launch_mul(dis, v, y, K, P->stream), "mul");
+      apply_op<double>(P, g, y, Ay);
+      hip_check(launch_lanczos_w(dis, Ay, vprev, b2prev, w, K, P->stream), "lanczos");
+      dot_op<double, double>(P, w, v, K, sa);                                       // a
+      hip_check(launch_axpy(-1.0, P->slot(sa), v, w, K, P->stream), "axpy");     // w -= a v
+      dot_op<double, double>(P, w, w, K, sb);                                       // b^2
+      std::swap(vprev, v);   // vprev <- v
+      hip_check(launch_scale_copy<double, double>(w, v, K, 1.0, P->slot(sb), P->stream), "scale");
+      b2prev = P->slot(sb);
+    }
+    P->read_slots(kLanczosSlot0 + 1, 2 * nb, h.data());
+    for (int i = 0; i < nb; ++i, ++j) {
+      const double a = h[size_t(2 * i)], b = std::sqrt(h[size_t(2 * i + 1)]);
+      al.push_back(a);
+      if (j == m - 1 || b <= 1e-12 * std::fabs(a)) {
+        done = true;
+        break;
+      }
+      be.push_back(b);
+    }
   }
   be.resize(al.size() > 0 ? al.size() - 1 : 0);
   return tridiag_max_eig(al, be);

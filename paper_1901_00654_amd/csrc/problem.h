@@ -98,7 +98,8 @@ struct Level {
   int wl_groups = 0;
 };
 
-constexpr int kSlots = 16;
+constexpr int kSlots = 80;
+constexpr int kLanczosSlot0 = 16;   // slots 16.. hold the Lanczos scalars during setup
 
 struct Problem {
   int device = 0;

@@ -53,7 +53,7 @@ typedef enum {
     TS_EINVAL = -1,       /* an argument is out of range (message says which)       */
     TS_ENOMEM = -2,       /* device allocation failed                               */
     TS_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed             */
-    TS_ESINGULAR = -4,    /* the coarse matrix A_1 is not positive definite, i.e.
+    TS_ESINGULAR = -4,    /* the coarse matrix A_c is not positive definite, i.e.
                              an affine function vanishes at every data point and
                              the smoothing problem has no unique solution          */
     TS_EBREAKDOWN = -5    /* CG breakdown: p'Ap <= 0 or a non-finite scalar        */
@@ -77,6 +77,30 @@ typedef enum {
                              where kappa(A) is beyond single precision             */
 } ts_precision;
 
+typedef enum {
+    TS_PC_MG = 0,         /* one V-cycle (Alg. 7): MGCG, Alg. 8 (default)            */
+    TS_PC_NONE = 1,       /* no preconditioner: plain CG on A, the comparison method
+                             of Sec. 4 (Table 2 and 3, column CG)                   */
+    TS_PC_JACOBI = 2      /* z = D^-1 r with D = diag(A) (Alg. 5 plus the Kronecker
+                             diagonal of Lambda)                                    */
+} ts_preconditioner;
+
+typedef enum {
+    TS_SMOOTH_JACOBI = 0, /* damped Jacobi, Alg. 6 (default)                         */
+    TS_SMOOTH_SSOR = 1    /* symmetric successive over-relaxation (Sec. 3.2.2), on
+                             the levels whose A_g is assembled as a stencil; levels
+                             applied matrix-free keep damped Jacobi. Rows are swept
+                             in 4^d colour classes (j_1 mod 4, ..., j_d mod 4) in
+                             C order, forward then backward; rows of one class do
+                             not couple, so each class is updated at once         */
+} ts_smoother;
+
+typedef enum {
+    TS_COARSE_DIRECT = 0, /* A_c assembled and inverted once in FP64 (default)       */
+    TS_COARSE_CG = 1      /* matrix-free CG on A_c with the diagonal as
+                             preconditioner (Sec. 3.2.4), to coarse_tol           */
+} ts_coarse_solver;
+
 typedef struct {
     int nu1, nu2;          /* pre/post Jacobi sweeps per level (Alg. 7); default 2, 2 */
     double omega_scale;    /* omega_g = omega_scale / theta_g, theta_g the largest
@@ -98,6 +122,17 @@ typedef struct {
                               1 = none (matrix-free on every level),
                               2 = every level whose stencil fits in memory          */
     void* stream;          /* hipStream_t to enqueue on; NULL = a library stream      */
+    int preconditioner;    /* ts_preconditioner; default TS_PC_MG (solve-time)       */
+    int smoother;          /* ts_smoother; default TS_SMOOTH_JACOBI (solve-time)    */
+    double ssor_omega;     /* SSOR relaxation factor in (0, 2); default 1 (symmetric
+                              Gauss-Seidel)                                         */
+    int coarse_solver;     /* ts_coarse_solver; default TS_COARSE_DIRECT             */
+    double coarse_tol;     /* TS_COARSE_CG: relative residual of the coarse solve;
+                              default 1e-14                                         */
+    int coarse_max_iter;   /* TS_COARSE_CG: most iterations per coarse solve; 20000 */
+    int coarsest_level;    /* c: the V-cycle recurses down to level c and solves A_c
+                              there (Sec. 3.2.1, 3.2.4); 1 <= c <= G, default 1; the
+                              direct solver needs K_c <= 8192                        */
 } ts_options;
 
 typedef struct {
@@ -109,6 +144,13 @@ typedef struct {
     double setup_s;        /* wall time of ts_create                                 */
     double solve_s;        /* wall time of this ts_solve                             */
     int64_t applies;       /* operator applies (any level, any precision) performed  */
+    const double* residual_history;  /* host, history_len entries: the recursive relative
+                              residual ||r_k|| / ||b|| before iteration 1 (k = 0) and
+                              after each CG iteration (mixed modes: the FP32 one,
+                              replaced by the FP64 true residual at each update);
+                              owned by the problem, valid until its next ts_solve or
+                              ts_destroy                                           */
+    int history_len;
 } ts_solve_info;
 
 /* Fills *opt with the defaults listed above. */
@@ -120,9 +162,10 @@ const char* ts_version(void);
 /*
  * Creates a smoothing problem (Sec. 2.2) and runs all setup on the device:
  * bins and sorts the points by knot cell, builds the level hierarchy
- * g = 1..G with G = log2(N) (Sec. 3.2.1), the Jacobi diagonals (Alg. 5 plus
- * the Kronecker diagonal of Lambda, Sec. 3.2.2), the damping omega_g, the
- * coarse matrix A_1 and its inverse (Sec. 3.2.4).
+ * g = c..G with G = log2(N) and c = opt.coarsest_level (Sec. 3.2.1), the
+ * Jacobi diagonals (Alg. 5 plus the Kronecker diagonal of Lambda, Sec. 3.2.2),
+ * the damping omega_g, and the coarse solver of level c: A_c and its inverse,
+ * or the data of the coarse CG (Sec. 3.2.4).
  *   d          dimension, 1 <= d <= 5
  *   q          spline degree; must be 3
  *   intervals  d ints, knot intervals per dimension; all equal to one power of
@@ -152,9 +195,12 @@ ts_status ts_create(int d, int q, const int32_t* intervals, const double* lo,
 void ts_destroy(ts_problem* p);
 
 /* Replaces the solve-time options of a problem: nu1, nu2, precision, max_iter,
- * tol, inner_tol and max_refine. Setup-time fields (omega_scale, lanczos_steps,
- * omega_fixed, points_per_block, stream) are ignored. Returns TS_EINVAL for
- * negative smoothing counts, tol <= 0 or an unknown precision. */
+ * tol, inner_tol, max_refine, preconditioner, smoother, ssor_omega, coarse_tol
+ * and coarse_max_iter. Setup-time fields (omega_scale, lanczos_steps,
+ * omega_fixed, points_per_block, stencil_mode, coarse_solver, coarsest_level,
+ * stream) are ignored. Returns TS_EINVAL for negative smoothing counts,
+ * tol <= 0, an unknown precision, preconditioner or smoother, or ssor_omega
+ * outside (0, 2). */
 ts_status ts_set_options(ts_problem* p, const ts_options* opt);
 
 /* Number of levels G (finest level index). */
@@ -163,35 +209,37 @@ ts_status ts_num_levels(const ts_problem* p, int* G);
 /* K_g = (N_g + 3)^d for level 1 <= g <= G (Sec. 3.2.1). */
 ts_status ts_num_coeffs(const ts_problem* p, int level, int64_t* K);
 
-/* The damping omega_g used by the Jacobi smoother on level g (2 <= g <= G; level 1
- * is solved exactly and reports 0). */
+/* The damping omega_g used by the Jacobi smoother on level g (1 <= g <= G; the
+ * coarsest level c and the levels below it report 0). */
 ts_status ts_get_omega(const ts_problem* p, int level, double* omega);
 
 /* b = Phi_G' y on the finest level (Alg. 3; first line of Alg. 8). b: device, K_G doubles. */
 ts_status ts_rhs(ts_problem* p, double* b);
 
 /* out = A_g c = (Phi_g'Phi_g + lambda Lambda_g) c (Alg. 4 then Alg. 3, plus Alg. 2 over
- * the Kronecker terms of Lambda, Sec. 2.4). c, out: device, K_g doubles, must not
- * alias. */
+ * the Kronecker terms of Lambda, Sec. 2.4), c <= g <= G. c, out: device, K_g doubles,
+ * must not alias. */
 ts_status ts_apply(ts_problem* p, int level, const double* c, double* out);
 
 /* The same operator evaluated in FP32 arithmetic (the inner operator of the mixed
  * modes; basis values from FP32 cell coordinates). c, out: device, K_g floats. */
 ts_status ts_apply_f32(ts_problem* p, int level, const float* c, float* out);
 
-/* D = diag(A_g) (Alg. 5 for Phi_g'Phi_g plus lambda diag(Lambda_g), Sec. 3.2.2).
- * D: device, K_g doubles. */
+/* D = diag(A_g) (Alg. 5 for Phi_g'Phi_g plus lambda diag(Lambda_g), Sec. 3.2.2),
+ * c <= g <= G. D: device, K_g doubles. */
 ts_status ts_diag(ts_problem* p, int level, double* D);
 
 /* out = I_{g-1}^{g} e: prolongation from level g-1 to g by the subdivision matrix
- * (eq. 2.6), 2 <= g <= G. e: device K_{g-1} doubles; out: device K_g doubles. */
+ * (eq. 2.6), c < g <= G. e: device K_{g-1} doubles; out: device K_g doubles. */
 ts_status ts_prolong(ts_problem* p, int level, const double* e, double* out);
 
-/* out = (I_{g-1}^{g})' r: restriction from level g to g-1 (Sec. 3.2.3), 2 <= g <= G.
+/* out = (I_{g-1}^{g})' r: restriction from level g to g-1 (Sec. 3.2.3), c < g <= G.
  * r: device K_g doubles; out: device K_{g-1} doubles. */
 ts_status ts_restrict(ts_problem* p, int level, const double* r, double* out);
 
-/* x = A_1^-1 b on the coarsest level (Sec. 3.2.4). b, x: device, K_1 doubles. */
+/* x = A_c^-1 b on the coarsest level c (Sec. 3.2.4) by the configured coarse solver
+ * (TS_COARSE_CG reads residual norms back, so it synchronises the stream every
+ * few iterations). b, x: device, K_c doubles. */
 ts_status ts_coarse_solve(ts_problem* p, const double* b, double* x);
 
 /* z = one V-cycle (Alg. 7) applied to r from a zero start on the finest level, i.e.
@@ -320,10 +368,12 @@ ts_status ts_server_submit(ts_server* s, const ts_request* req, uint64_t* ticket
 ts_status ts_server_poll(ts_server* s, uint64_t ticket, int* done);
 
 /* Blocks until the request has finished, copies its solution (K doubles, C
- * order, finest level) into the HOST buffer alpha when alpha is not NULL and
- * capacity >= K, fills *result (may be NULL) and releases the ticket. Returns
- * TS_EINVAL for an unknown or already released ticket or a too small buffer;
- * the request's own outcome is result->status. */
+ * order, finest level) into the HOST buffer alpha when alpha is not NULL,
+ * fills *result (may be NULL) and releases the ticket. Any thread may wait,
+ * but only one at a time per ticket. Returns TS_EINVAL, without waiting, for
+ * an unknown or already released ticket, a ticket another thread is already
+ * waiting for, or alpha != NULL with capacity < K; the request's own outcome
+ * is result->status. */
 ts_status ts_server_wait(ts_server* s, uint64_t ticket, double* alpha, int64_t capacity,
                          ts_result* result);
 

@@ -10,8 +10,15 @@ matrices of ``system.gram_1d``.
 points whose cell lies in the support of phi_k; it serves as the oracle for
 full-size problems, where the complete product is too slow on a CPU.
 
-Pinned by tests/test_oracle_matfree.py against the assembled ``system`` on
-small problems.
+``LevelOperator`` is A_g as an operator for the multigrid oracle at sizes
+where the Kronecker products of Lambda are too large to assemble: Phi_g as a
+sparse matrix, Lambda_g through its 1D factors. ``lambda_diagonal`` is the
+diagonal of Lambda from the diagonals of the 1D factors (the diagonal of a
+Kronecker product is the Kronecker product of the diagonals, Sec. 3.1.3).
+
+Pinned by tests/test_oracle_system.py (matrix-free products and rows,
+LevelOperator and lambda_diagonal) against the assembled ``system`` on small
+problems.
 """
 import itertools
 import math
@@ -140,3 +147,71 @@ def evaluate(alpha, xq, lo, hi, N, q=3):
     """s(x_q) = sum_k alpha_k phi_k(x_q) without assembly."""
     return phi_apply(np.atleast_2d(xq), np.asarray(alpha, dtype=np.float64),
                      lo, hi, N, q)
+
+
+def lambda_diagonal(d, lo, hi, N, q=3):
+    """diag(Lambda) = sum over |r| = 2 of (2/r!) kron_p diag(Psi^p_{r_p})."""
+    grams = _grams(d, lo, hi, N, q)
+    out = np.zeros((N + q) ** d)
+    for r, coef in _terms(d):
+        v = np.ones(1)
+        for p in range(d):
+            v = np.kron(v, np.diag(grams[p][r[p]]))
+        out += coef * v
+    return out
+
+
+class LevelOperator:
+    """A_g = Phi_g'Phi_g + lam Lambda_g as an operator (``@``, ``diagonal()``).
+
+    Phi_g is assembled sparse (n x K, (q+1)^d nonzeros per row, Sec. 2.4) and
+    applied as Phi_g'(Phi_g c); Lambda_g c goes through the 1D factors
+    (``lambda_apply``). The diagonal is the column sums of Phi_g squared
+    (Alg. 5) plus lam times ``lambda_diagonal``.
+    """
+
+    def __init__(self, x, lo, hi, N, lam, q=3):
+        x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+        self.d = x.shape[1]
+        self.lo, self.hi, self.N, self.lam, self.q = lo, hi, N, lam, q
+        self.Phi = system.phi_matrix(x, lo, hi, N, q).tocsr()
+        self.PhiT = self.Phi.T.tocsr()
+        K = (N + q) ** self.d
+        self.shape = (K, K)
+        self._diag = (np.asarray(self.Phi.multiply(self.Phi).sum(axis=0)).ravel()
+                      + lam * lambda_diagonal(self.d, lo, hi, N, q))
+
+    def __matmul__(self, c):
+        c = np.asarray(c, dtype=np.float64)
+        return (self.PhiT @ (self.Phi @ c)
+                + self.lam * lambda_apply(c, self.d, self.lo, self.hi, self.N, self.q))
+
+    def diagonal(self):
+        return self._diag
+
+
+def operator_hierarchy(x, y, lo, hi, N, lam, q=3, G=None, coarsest=1):
+    """Levels c..G for ``mg.MG(levels=...)`` without assembling A_g above c.
+
+    Level g > c holds a ``LevelOperator``; level c holds the dense A_c
+    (``system.normal_matrix_dense``); the finest level holds b = Phi'y; every
+    level above c holds the prolongation from the level below (eq. 2.6).
+    """
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    d = x.shape[1]
+    if G is None:
+        G = int(round(math.log2(N)))
+    levels = {}
+    for g in range(coarsest, G + 1):
+        Ng = N >> (G - g)
+        if g == coarsest:
+            lev = {"N": Ng, "A": system.normal_matrix_dense(x, lo, hi, Ng, lam, q)}
+        else:
+            lev = {"N": Ng, "A": LevelOperator(x, lo, hi, Ng, lam, q),
+                   "P": system.prolongation(d, Ng // 2, q)}
+        if g == G:
+            op = lev["A"]
+            lev["b"] = (op.PhiT @ np.asarray(y, dtype=np.float64) if isinstance(op, LevelOperator)
+                        else system.phi_matrix(x, lo, hi, Ng, q).T @ np.asarray(y, dtype=np.float64))
+        levels[g] = lev
+    return levels

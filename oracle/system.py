@@ -164,3 +164,43 @@ def hierarchy(x, y, lo, hi, N, lam, q=3, G=None):
 def evaluate(alpha, xq, lo, hi, N, q=3):
     """s(x) = sum_k alpha_k phi_k(x) at query points (eq. 2.2)."""
     return phi_matrix(xq, lo, hi, N, q) @ np.asarray(alpha, dtype=np.float64)
+
+
+def normal_matrix_dense(x, lo, hi, N, lam, q=3):
+    """Dense A = Phi'Phi + lam Lambda with Phi'Phi summed cell by cell.
+
+    The points of one knot cell share their (q+1)^d nonzero basis indices, so
+    Phi'Phi = sum over cells of B_c' B_c with B_c the dense (points x (q+1)^d)
+    block of those rows, added into the rows and columns of the cell's patch
+    (the per-cell Gram blocks of the survey's oracle recipe). Same matrix as
+    ``system`` (pinned there); practical where K is a few thousand.
+    """
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    n, d = x.shape
+    J = N + q
+    cells, vals = [], []
+    for p in range(d):
+        c, V = bspline.basis_local(x[:, p], lo[p], hi[p], N, q)
+        cells.append(c)
+        vals.append(V)
+    flat_cell = np.zeros(n, dtype=np.int64)
+    for p in range(d):
+        flat_cell = flat_cell * N + cells[p]
+    A = lambda_matrix(d, lo, hi, N, q).toarray() * lam
+    order = np.argsort(flat_cell, kind="stable")
+    bounds = np.flatnonzero(np.diff(flat_cell[order])) + 1
+    offsets = list(itertools.product(range(q + 1), repeat=d))
+    for grp in np.split(order, bounds):
+        if grp.size == 0:
+            continue
+        i0 = grp[0]
+        B = np.ones((grp.size, len(offsets)))
+        idx = np.zeros(len(offsets), dtype=np.int64)
+        for m, a in enumerate(offsets):
+            k = 0
+            for p in range(d):
+                k = k * J + cells[p][i0] + a[p]
+                B[:, m] *= vals[p][grp, a[p]]
+            idx[m] = k
+        A[np.ix_(idx, idx)] += B.T @ B
+    return A

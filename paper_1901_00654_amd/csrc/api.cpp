@@ -56,6 +56,13 @@ void ts_default_options(ts_options* o) {
   o->points_per_block = 0;
   o->stencil_mode = 0;
   o->stream = nullptr;
+  o->preconditioner = TS_PC_MG;
+  o->smoother = TS_SMOOTH_JACOBI;
+  o->ssor_omega = 1.0;
+  o->coarse_solver = TS_COARSE_DIRECT;
+  o->coarse_tol = 1e-14;
+  o->coarse_max_iter = 20000;
+  o->coarsest_level = 1;
 }
 
 const char* ts_version(void) { return "tsmg 0.1 gfx950"; }
@@ -90,9 +97,12 @@ ts_status ts_set_options(ts_problem* p, const ts_options* opt) {
   TS_API_BEGIN
   Problem* P = get(p);
   need(opt != nullptr, "opt must not be null");
-  need(opt->nu1 >= 0 && opt->nu2 >= 0, "nu1, nu2 must be >= 0");
-  need(opt->tol > 0.0 && opt->max_iter >= 0 && opt->max_refine >= 0, "tol must be > 0, limits >= 0");
-  need(tsmg::precision_available(opt->precision), "unknown or unavailable precision");
+  tsmg::check_solve_options(*opt);
+  P->opt.preconditioner = opt->preconditioner;
+  P->opt.smoother = opt->smoother;
+  P->opt.ssor_omega = opt->ssor_omega;
+  P->opt.coarse_tol = opt->coarse_tol;
+  P->opt.coarse_max_iter = opt->coarse_max_iter;
   P->opt.nu1 = opt->nu1;
   P->opt.nu2 = opt->nu2;
   P->opt.precision = opt->precision;
@@ -128,7 +138,7 @@ ts_status ts_get_omega(const ts_problem* p, int level, double* omega) {
   Problem* P = get(p);
   need(omega != nullptr, "omega must not be null");
   check_level(P, level, 1);
-  *omega = (level == 1) ? 0.0 : P->lev[level].omega;
+  *omega = (level <= P->Gc) ? 0.0 : P->lev[level].omega;
   return TS_OK;
   TS_API_END
 }
@@ -145,7 +155,7 @@ ts_status ts_rhs(ts_problem* p, double* b) {
 ts_status ts_apply(ts_problem* p, int level, const double* c, double* out) {
   TS_API_BEGIN
   Problem* P = get(p);
-  check_level(P, level, 1);
+  check_level(P, level, P->Gc);
   need(c && out, "c and out must not be null");
   need(static_cast<const void*>(c) != static_cast<const void*>(out), "c and out must not alias");
   tsmg::apply_op<double>(P, level, c, out);
@@ -156,7 +166,7 @@ ts_status ts_apply(ts_problem* p, int level, const double* c, double* out) {
 ts_status ts_apply_f32(ts_problem* p, int level, const float* c, float* out) {
   TS_API_BEGIN
   Problem* P = get(p);
-  check_level(P, level, 1);
+  check_level(P, level, P->Gc);
   need(c && out, "c and out must not be null");
   need(static_cast<const void*>(c) != static_cast<const void*>(out), "c and out must not alias");
   tsmg::apply_op<float>(P, level, c, out);
@@ -167,7 +177,7 @@ ts_status ts_apply_f32(ts_problem* p, int level, const float* c, float* out) {
 ts_status ts_diag(ts_problem* p, int level, double* D) {
   TS_API_BEGIN
   Problem* P = get(p);
-  check_level(P, level, 1);
+  check_level(P, level, P->Gc);
   need(D != nullptr, "D must not be null");
   const tsmg::Level& L = P->lev[level];
   tsmg::hip_check(hipMemcpyAsync(D, L.diag.p, sizeof(double) * L.K, hipMemcpyDeviceToDevice, P->stream),
@@ -179,7 +189,7 @@ ts_status ts_diag(ts_problem* p, int level, double* D) {
 ts_status ts_prolong(ts_problem* p, int level, const double* e, double* out) {
   TS_API_BEGIN
   Problem* P = get(p);
-  check_level(P, level, 2);
+  check_level(P, level, P->Gc + 1);
   need(e && out, "e and out must not be null");
   tsmg::prolong_op<double>(P, level, e, out, false);
   return TS_OK;
@@ -189,7 +199,7 @@ ts_status ts_prolong(ts_problem* p, int level, const double* e, double* out) {
 ts_status ts_restrict(ts_problem* p, int level, const double* r, double* out) {
   TS_API_BEGIN
   Problem* P = get(p);
-  check_level(P, level, 2);
+  check_level(P, level, P->Gc + 1);
   need(r && out, "r and out must not be null");
   tsmg::restrict_op<double>(P, level, r, out, static_cast<const double*>(nullptr));
   return TS_OK;

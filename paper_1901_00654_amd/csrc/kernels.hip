@@ -1713,6 +1713,62 @@ __global__ __launch_bounds__(kBlock) void k_stencil_apply_small(const T* S, int 
   }
 }
 
+// One colour class of the SSOR sweep (Sec. 3.2.2) on a stencil level: the
+// rows k whose multi-index has j_p = c_p (mod 4) in every dimension, c the
+// class's base-4 digits in C order. Two rows of a class are at least four
+// apart in some dimension, outside each other's 7^d stencil, so the class is
+// updated at once and in place:
+//   x_k <- x_k + omega (b_k - (A x)_k) / A_kk.
+// Same row layout as k_stencil_apply_small (8 rows per block, 32 threads per
+// row); every read of x in a block precedes the barrier, every write follows it.
+template <typename T, int D>
+__global__ __launch_bounds__(kBlock) void k_stencil_color(const T* S, int J, T* x, const T* b, T omega, int color,
+                                                          int64_t rows, int64_t K) {
+  constexpr int NH = stencil_half<D>();
+  constexpr int PER = (NH + kStSmallCols - 1) / kStSmallCols;
+  __shared__ T part[kBlock / 64][kStSmallRows];
+  const int r = threadIdx.x % kStSmallRows;
+  const int c = threadIdx.x / kStSmallRows;
+  const int64_t q = int64_t(blockIdx.x) * kStSmallRows + r;   // row of the class
+  int64_t k = -1;
+  if (q < rows) {
+    int64_t rem = q, kk = 0, stride = 1;
+    int col = color;
+#pragma unroll
+    for (int p = D - 1; p >= 0; --p) {
+      const int cp = col % 4;
+      col /= 4;
+      const int64_t m = (J - cp + 3) / 4;
+      const int64_t ip = rem % m;
+      rem /= m;
+      kk += (cp + 4 * ip) * stride;
+      stride *= J;
+    }
+    k = kk;
+  }
+  T a0 = T(0), a1 = T(0);
+  if (k >= 0) {
+#pragma unroll
+    for (int s = 0; s < PER; ++s) {
+      const int h = c + s * kStSmallCols;
+      if (h < NH) stencil_pair<T, D, kStPlain>(S, J, x, nullptr, nullptr, K, k, h, a0, a1);
+    }
+  }
+  T a = a0 + a1;
+  a += __shfl_xor(a, 8);
+  a += __shfl_xor(a, 16);
+  a += __shfl_xor(a, 32);
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  if (lane < kStSmallRows) part[wv][lane] = a;
+  __syncthreads();
+  if (threadIdx.x < kStSmallRows && k >= 0) {
+    T v = part[0][r];
+#pragma unroll
+    for (int s = 1; s < kBlock / 64; ++s) v += part[s][r];
+    x[k] = x[k] + omega * (b[k] - v) / S[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.
 static inline unsigned blocks_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
@@ -2185,6 +2241,39 @@ hipError_t launch_stencil_apply(int D, int epi, const T* S, int J, const T* x, T
   if (epi == kStJacobiZero) return launch_stencil_epi<T, kStJacobiZero>(D, S, J, x, out, b, w, K, st);
   return hipErrorInvalidValue;
 }
+
+template <typename T, int D>
+static hipError_t launch_stencil_color_d(const T* S, int J, T* x, const T* b, T omega, int color, int64_t K,
+                                         hipStream_t st) {
+  int64_t rows = 1;
+  int col = color;
+  for (int p = D - 1; p >= 0; --p) {
+    const int cp = col % 4;
+    col /= 4;
+    rows *= (J - cp + 3) / 4;
+  }
+  if (rows <= 0) return hipSuccess;
+  const unsigned nb = unsigned((rows + kStSmallRows - 1) / kStSmallRows);
+  hipLaunchKernelGGL((k_stencil_color<T, D>), dim3(nb), dim3(kBlock), 0, st, S, J, x, b, omega, color, rows, K);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_stencil_color(int D, const T* S, int J, T* x, const T* b, T omega, int color, int64_t K,
+                                hipStream_t st) {
+  switch (D) {
+    case 1: return launch_stencil_color_d<T, 1>(S, J, x, b, omega, color, K, st);
+    case 2: return launch_stencil_color_d<T, 2>(S, J, x, b, omega, color, K, st);
+    case 3: return launch_stencil_color_d<T, 3>(S, J, x, b, omega, color, K, st);
+    case 4: return launch_stencil_color_d<T, 4>(S, J, x, b, omega, color, K, st);
+    case 5: return launch_stencil_color_d<T, 5>(S, J, x, b, omega, color, K, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_stencil_color<double>(int, const double*, int, double*, const double*, double, int,
+                                                 int64_t, hipStream_t);
+template hipError_t launch_stencil_color<float>(int, const float*, int, float*, const float*, float, int, int64_t,
+                                                hipStream_t);
 template hipError_t launch_stencil_apply<double>(int, int, const double*, int, const double*, double*,
                                                  const double*, const double*, int64_t, hipStream_t);
 template hipError_t launch_stencil_apply<float>(int, int, const float*, int, const float*, float*, const float*,

@@ -125,6 +125,13 @@ template <typename T>
 hipError_t launch_stencil_apply(int D, int epi, const T* S, int J, const T* x, T* out, const T* b, const T* w,
                                 int64_t K, hipStream_t st);
 
+// One colour class of the SSOR sweep on a stencil level, in place:
+// x_k += omega (b_k - (A x)_k) / A_kk for the rows with j_p = c_p (mod 4),
+// c_p the base-4 digits of `color` (C order); 4^D classes.
+template <typename T>
+hipError_t launch_stencil_color(int D, const T* S, int J, T* x, const T* b, T omega, int color, int64_t K,
+                                hipStream_t st);
+
 // Radix sort of (key, index) pairs on the low `bits` bits (sort.hip).
 hipError_t sort_pairs(uint32_t* key_in, uint32_t* key_out, uint32_t* val_in, uint32_t* val_out, int64_t n,
                       int bits, void* tmp, size_t* tmp_bytes, hipStream_t st);

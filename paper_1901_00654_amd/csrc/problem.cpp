@@ -511,25 +511,81 @@ void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub) {
 template void restrict_op<double>(Problem*, int, const double*, double*, const double*);
 template void restrict_op<float>(Problem*, int, const float*, float*, const float*);
 
-// x = A_1^-1 b with the precomputed inverse B and one refinement step:
-// x1 = B b, r = b - A_1 x1, x = x1 + B r (all FP64), so the result is as
-// accurate as a backward-stable solve would give.
+// Coarse CG slots (the outer Krylov loop uses 0..7, Lanczos 16..).
+enum CoarseSlot : int { kCbb = 8, kCrzA = 9, kCrzB = 10, kCpv = 11, kCrr = 12 };
+
+// x = A_c^-1 b on the coarsest level c (Sec. 3.2.4).
+// Direct: the precomputed inverse B and one refinement step, x1 = B b,
+// r = b - A_c x1, x = x1 + B r (all FP64), as accurate as a backward-stable
+// solve. CG: matrix-free CG on A_c with D_c^-1 as preconditioner from x = 0,
+// in FP64, until ||r|| <= coarse_tol ||b|| or coarse_max_iter iterations; the
+// residual norm is read back every few iterations.
 template <typename T>
 void coarse_op(Problem* P, const T* b, T* x) {
   const int K = P->K1;
-  double* x1 = P->cwork.p;
-  double* r = P->cwork.p + K;
-  hip_check(launch_gemv<double, T, double>(P->A1inv.p, K, nullptr, 1.0, b, x1, P->stream), "coarse solve");
-  hip_check(launch_gemv<T, double, double>(P->A1.p, K, b, -1.0, x1, r, P->stream), "coarse residual");
-  hip_check(launch_gemv<double, double, T>(P->A1inv.p, K, x1, 1.0, r, x, P->stream), "coarse correction");
+  if (P->opt.coarse_solver != TS_COARSE_CG) {
+    double* x1 = P->cwork.p;
+    double* r = P->cwork.p + K;
+    hip_check(launch_gemv<double, T, double>(P->A1inv.p, K, nullptr, 1.0, b, x1, P->stream), "coarse solve");
+    hip_check(launch_gemv<T, double, double>(P->A1.p, K, b, -1.0, x1, r, P->stream), "coarse residual");
+    hip_check(launch_gemv<double, double, T>(P->A1inv.p, K, x1, 1.0, r, x, P->stream), "coarse correction");
+    return;
+  }
+  hipStream_t st = P->stream;
+  const int c = P->Gc;
+  double *cx = P->cx.p, *cr = P->cr.p, *cz = P->cz.p, *cp = P->cp.p, *cv = P->cv.p;
+  hip_check(launch_scale_copy<T, double>(b, cr, K, 1.0, nullptr, st), "coarse copy");
+  hip_check(launch_fill<double>(cx, 0.0, K, st), "fill");
+  dot_op<double, double>(P, cr, cr, K, kCbb);
+  hip_check(launch_mul(P->cdinv.p, cr, cz, K, st), "coarse precondition");
+  hip_check(launch_scale_copy<double, double>(cz, cp, K, 1.0, nullptr, st), "copy");
+  int sa = kCrzA, sb = kCrzB;
+  dot_op<double, double>(P, cr, cz, K, sa);
+  const double tol = P->opt.coarse_tol > 0.0 ? P->opt.coarse_tol : 1e-14;
+  const int maxit = P->opt.coarse_max_iter > 0 ? P->opt.coarse_max_iter : 20000;
+  constexpr int kCheck = 8;
+  for (int it = 0; it < maxit;) {
+    for (int j = 0; j < kCheck && it < maxit; ++j, ++it) {
+      apply_op<double>(P, c, cp, cv);
+      dot_op<double, double>(P, cp, cv, K, kCpv);
+      hip_check(launch_cg_step<double, double>(cx, cr, cp, cv, K, P->slot(sa), P->slot(kCpv), st), "coarse step");
+      hip_check(launch_mul(P->cdinv.p, cr, cz, K, st), "coarse precondition");
+      dot_op<double, double>(P, cr, cz, K, sb);
+      hip_check(launch_p_update<double>(cp, cz, K, P->slot(sb), P->slot(sa), st), "coarse p update");
+      std::swap(sa, sb);
+      ++P->coarse_iters;
+    }
+    dot_op<double, double>(P, cr, cr, K, kCrr);
+    double h[5];
+    P->read_slots(kCbb, 5, h);
+    const double bb = h[0], rr = h[kCrr - kCbb];
+    if (!(bb > 0.0) || !(rr > tol * tol * bb)) break;
+  }
+  hip_check(launch_scale_copy<double, T>(cx, x, K, 1.0, nullptr, st), "coarse copy");
 }
 template void coarse_op<double>(Problem*, const double*, double*);
 template void coarse_op<float>(Problem*, const float*, float*);
 
+// One symmetric SSOR step on a stencil level (Sec. 3.2.2): the 4^d colour
+// classes forward, then backward; each class update is
+// x_k += omega (b_k - (A x)_k) / A_kk for every row k of the class at once.
+template <typename T>
+static void ssor_step(Problem* P, int g, T* x, const T* b) {
+  Level& L = P->lev[g];
+  int ncol = 1;
+  for (int p = 0; p < P->d; ++p) ncol *= 4;
+  const T w = T(P->opt.ssor_omega);
+  for (int c = 0; c < ncol; ++c)
+    hip_check(launch_stencil_color<T>(P->d, lvl_S<T>(L), L.J, x, b, w, c, L.K, P->stream), "ssor");
+  for (int c = ncol - 1; c >= 0; --c)
+    hip_check(launch_stencil_color<T>(P->d, lvl_S<T>(L), L.J, x, b, w, c, L.K, P->stream), "ssor");
+  P->applies += 2;
+}
+
 // One V-cycle (Alg. 7) on level g from a zero start: alpha = B_g b.
 template <typename T>
 void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
-  if (g == 1) {
+  if (g == P->Gc) {
     coarse_op<T>(P, b, alpha);
     return;
   }
@@ -539,6 +595,18 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
   T* t = lvl_t<T>(L);
   const T* w = lvl_w<T>(L);
   const int nu1 = P->opt.nu1, nu2 = P->opt.nu2;
+  if (L.stencil && P->opt.smoother == TS_SMOOTH_SSOR) {
+    // SSOR steps in place on alpha; the residual through the stencil product
+    hip_check(launch_fill<T>(alpha, T(0), K, P->stream), "fill");
+    for (int j = 0; j < nu1; ++j) ssor_step<T>(P, g, alpha, b);
+    hip_check(launch_stencil_apply<T>(P->d, 2, lvl_S<T>(L), L.J, alpha, t, b, w, K, P->stream), "residual");
+    P->applies++;
+    restrict_op<T>(P, g, t, lvl_b<T>(C), static_cast<const T*>(nullptr));
+    vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
+    prolong_op<T>(P, g, lvl_a<T>(C), alpha, true);
+    for (int j = 0; j < nu2; ++j) ssor_step<T>(P, g, alpha, b);
+    return;
+  }
   if (L.stencil) {
     // Jacobi sweeps fused into the stencil product, ping-ponging between
     // alpha and t; the first sweep lands so that the last one ends in alpha.
@@ -828,7 +896,9 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
   // sort scratch bounded by another key/value pair and 1 MB)
   const int64_t sort_tmp = 24 * n + (1 << 20);
   int64_t levels = 0, stencils = 0, stencil_tmp = 0;
-  for (int g = 1; g <= G; ++g) {
+  const int Gc = std::max(1, std::min(G, opt.coarsest_level));
+  const bool direct = opt.coarse_solver != TS_COARSE_CG;
+  for (int g = Gc; g <= G; ++g) {
     const int J = (1 << g) + kDeg;
     const int64_t K = ipow(J, d);
     levels += 56 * K + int64_t(d) * 3 * J * 7 * 12;
@@ -840,16 +910,16 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
       const int64_t chunks = std::min(n, ntiles) + n / 64 + 2;
       levels += 20 * chunks + 4 * n + 4;
     }
-    // level 1 always carries its stencil: A_1 is expanded from it
-    if (g == 1 || st) {
+    // with the direct coarse solver level c carries its stencil: A_c is expanded from it
+    if ((g == Gc && direct) || st) {
       stencils += (ipow(7, d) + 1) / 2 * K * 12;   // the stored half, FP64 + FP32
       // two pass buffers, plus the moments handed on to level g-1
       const int64_t coarser = g > 1 ? ipow(7 * int64_t(1 << (g - 1)), d) * 8 : 0;
       stencil_tmp = std::max(stencil_tmp, 2 * ipow(7 * int64_t(J), d) * 8 + coarser + (1 << 16));
     }
   }
-  const int64_t K1 = ipow(2 + kDeg, d);
-  const int64_t coarse = 2 * K1 * K1 * 8 + 2 * K1 * 8;
+  const int64_t K1 = ipow((int64_t(1) << Gc) + kDeg, d);
+  const int64_t coarse = direct ? 2 * K1 * K1 * 8 + 2 * K1 * 8 : 6 * K1 * 8 + K1 * 4;
   const int64_t finest = KG * (6 * 12 + 2 * 12 + 5 * 8 + 5 * 4);
   const int64_t misc = 16 * 8 + kMaxPartials * 8 + 64;
   const int64_t steady = points + levels + stencils + coarse + finest + misc;
@@ -858,17 +928,32 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
   return steady + std::max(sort_tmp, stencil_tmp) + slack;
 }
 
-// A_1 expanded from the level-1 stencil (built here if the apply path did
-// not build it), then inverted by Gauss-Jordan; pivots checked for
-// positivity.
+// The coarse solver of level c (Sec. 3.2.4). Direct: A_c expanded from the
+// level-c stencil (built here if the apply path did not build it), then
+// inverted by Gauss-Jordan; pivots checked for positivity. CG: the inverse
+// diagonal and the CG vectors of level c.
 static void build_coarse(Problem* P) {
   const int D = P->d;
-  Level& L1 = P->lev[1];
+  const int c = P->Gc;
+  Level& L1 = P->lev[c];
   const int64_t K1 = L1.K;
   P->K1 = int(K1);
+  if (P->opt.coarse_solver == TS_COARSE_CG) {
+    P->cdinv.alloc(size_t(K1));
+    P->cx.alloc(size_t(K1));
+    P->cr.alloc(size_t(K1));
+    P->cz.alloc(size_t(K1));
+    P->cp.alloc(size_t(K1));
+    P->cv.alloc(size_t(K1));
+    DevBuf<float> unused;
+    unused.alloc(size_t(K1));
+    hip_check(launch_wdinv(L1.diag.p, 1.0, P->cdinv.p, unused.p, K1, P->stream), "coarse dinv");
+    hip_check(hipStreamSynchronize(P->stream), "sync");
+    return;
+  }
   if (!L1.S64.p) {
     DevBuf<double> none;
-    build_stencil(P, 1, none, false);
+    build_stencil(P, c, none, false);
     L1.stencil = (P->opt.stencil_mode != 1);
   }
   DevBuf<double> row, col, piv;
@@ -898,10 +983,23 @@ static void build_coarse(Problem* P) {
     const double dkk = a1[size_t(k) * K1 + k];
     if (!std::isfinite(pv[k]) || !(pv[k] > 1e-13 * dkk)) {
       throw Error{TS_ESINGULAR,
-                  "coarse matrix A_1 is not positive definite (pivot " + std::to_string(k) + " = " +
-                      std::to_string(pv[k]) + "): some affine function vanishes at every data point"};
+                  "coarse matrix A_" + std::to_string(c) + " is not positive definite (pivot " + std::to_string(k) +
+                      " = " + std::to_string(pv[k]) + "): some affine function vanishes at every data point"};
     }
   }
+}
+
+void check_solve_options(const ts_options& o) {
+  if (o.nu1 < 0 || o.nu2 < 0) throw Error{TS_EINVAL, "nu1, nu2 must be >= 0"};
+  if (!precision_available(o.precision)) throw Error{TS_EINVAL, "unknown or unavailable precision"};
+  if (!(o.tol > 0.0)) throw Error{TS_EINVAL, "tol must be > 0"};
+  if (o.max_iter < 0 || o.max_refine < 0) throw Error{TS_EINVAL, "iteration limits must be >= 0"};
+  if (o.preconditioner != TS_PC_MG && o.preconditioner != TS_PC_NONE && o.preconditioner != TS_PC_JACOBI)
+    throw Error{TS_EINVAL, "unknown preconditioner"};
+  if (o.smoother != TS_SMOOTH_JACOBI && o.smoother != TS_SMOOTH_SSOR) throw Error{TS_EINVAL, "unknown smoother"};
+  if (o.smoother == TS_SMOOTH_SSOR && !(o.ssor_omega > 0.0 && o.ssor_omega < 2.0))
+    throw Error{TS_EINVAL, "ssor_omega must be in (0, 2)"};
+  if (o.coarse_tol < 0.0 || o.coarse_max_iter < 0) throw Error{TS_EINVAL, "coarse CG limits must be >= 0"};
 }
 
 Problem* create_problem(int d, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
@@ -939,10 +1037,19 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     P->lam = lam;
     ts_default_options(&P->opt);
     if (opt) P->opt = *opt;
-    if (P->opt.nu1 < 0 || P->opt.nu2 < 0) throw Error{TS_EINVAL, "nu1, nu2 must be >= 0"};
-    if (!precision_available(P->opt.precision))
-      throw Error{TS_EINVAL, "unknown or unavailable precision"};
-    if (!(P->opt.tol > 0.0)) throw Error{TS_EINVAL, "tol must be > 0"};
+    check_solve_options(P->opt);
+    if (P->opt.coarse_solver != TS_COARSE_DIRECT && P->opt.coarse_solver != TS_COARSE_CG)
+      throw Error{TS_EINVAL, "unknown coarse solver"};
+    if (P->opt.coarsest_level < 1 || P->opt.coarsest_level > G)
+      throw Error{TS_EINVAL, "coarsest_level must be in 1..G = " + std::to_string(G)};
+    P->Gc = P->opt.coarsest_level;
+    if (P->opt.coarse_solver == TS_COARSE_DIRECT) {
+      int64_t Kc = 1;
+      for (int p = 0; p < d; ++p) Kc *= (int64_t(1) << P->Gc) + kDeg;
+      if (Kc > kMaxDirectCoarse)
+        throw Error{TS_EINVAL, "the direct coarse solver takes K_c <= " + std::to_string(kMaxDirectCoarse) +
+                                   " coefficients (K_c = " + std::to_string(Kc) + "); use TS_COARSE_CG"};
+    }
     if (P->opt.omega_fixed <= 0.0 && !(P->opt.omega_scale > 0.0 && P->opt.omega_scale < 2.0))
       throw Error{TS_EINVAL, "omega_scale must be in (0, 2)"};
     hip_check(hipGetDevice(&P->device), "hipGetDevice");
@@ -1022,6 +1129,7 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
       L.K = 1;
       for (int p = 0; p < d; ++p) L.K *= L.J;
       L.tb = std::min(kTileBits[d], g);
+      if (g < P->Gc) continue;   // below the coarsest level: sizes only
       std::vector<double> band(size_t(d) * 3 * L.J * 7);
       for (int p = 0; p < d; ++p) {
         std::vector<double> b1;
@@ -1066,7 +1174,8 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
       const double budget = stencil_budget_for(stencil_budget);
       std::vector<char> want(size_t(G) + 1, 0);
       bool matrix_free = false;
-      for (int g = 1; g <= G; ++g) {
+      const int Gc = P->Gc;
+      for (int g = Gc; g <= G; ++g) {
         want[size_t(g)] = want_stencil(d, P->lev[g].J, n, P->opt.stencil_mode, budget);
         matrix_free = matrix_free || !want[size_t(g)];
       }
@@ -1080,26 +1189,26 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
       std::vector<int> tbs(size_t(G) + 1);
       for (int g = 1; g <= G; ++g) tbs[size_t(g)] = P->lev[g].tb;
       const int64_t ppb = P->ppb;
-      auto lists = std::async(std::launch::async, [&want, &off_h, tbs, ppb, d, G]() {
+      auto lists = std::async(std::launch::async, [&want, &off_h, tbs, ppb, d, G, Gc]() {
         std::vector<WorkListHost> r(size_t(G) + 1);
-        for (int g = 1; g <= G; ++g)
+        for (int g = Gc; g <= G; ++g)
           if (!want[size_t(g)]) r[size_t(g)] = make_worklist(d, G, g, tbs[size_t(g)], ppb, off_h);
         return r;
       });
       // finest first: each level's moments give the next coarser level's
       DevBuf<double> mom;
-      for (int g = G; g >= 1; --g) {
+      for (int g = G; g >= Gc; --g) {
         if (!want[size_t(g)]) { mom.reset(); continue; }
-        build_stencil(P, g, mom, g > 1 && want[size_t(g) - 1]);
+        build_stencil(P, g, mom, g > Gc && want[size_t(g) - 1]);
       }
       const std::vector<WorkListHost> wl = lists.get();
-      for (int g = 1; g <= G; ++g)
+      for (int g = Gc; g <= G; ++g)
         if (!want[size_t(g)]) upload_worklist(P, g, wl[size_t(g)]);
     }
 
     // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)
-    for (int g = 1; g <= G; ++g) compute_diag(P, g);
-    for (int g = 2; g <= G; ++g) {
+    for (int g = P->Gc; g <= G; ++g) compute_diag(P, g);
+    for (int g = P->Gc + 1; g <= G; ++g) {
       Level& L = P->lev[g];
       if (P->opt.omega_fixed > 0.0) {
         L.omega = P->opt.omega_fixed;
@@ -1108,6 +1217,14 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
         L.omega = P->opt.omega_scale / L.theta;
       }
       hip_check(launch_wdinv(L.diag.p, L.omega, L.wdinv64.p, L.wdinv32.p, L.K, st), "wdinv");
+    }
+
+    {   // D_G^-1 for the Jacobi preconditioner
+      DevBuf<float> unused;
+      unused.alloc(size_t(KG));
+      P->dinv_fine.alloc(size_t(KG));
+      hip_check(launch_wdinv(P->lev[G].diag.p, 1.0, P->dinv_fine.p, unused.p, KG, st), "dinv");
+      hip_check(hipStreamSynchronize(st), "sync");
     }
 
     // --- coarse level (Sec. 3.2.4)

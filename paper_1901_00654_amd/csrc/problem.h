@@ -21,6 +21,11 @@ void hip_check(hipError_t e, const char* what);
 inline bool precision_available(int p) {
   return p == TS_FP64 || p == TS_MIXED_FP32 || p == TS_MIXED_FP32_VCYCLE;
 }
+// Checks of the solve-time option fields shared by ts_create and
+// ts_set_options; throws Error{TS_EINVAL}.
+void check_solve_options(const ts_options& o);
+// Largest coarsest-level size the direct coarse solver inverts.
+constexpr int64_t kMaxDirectCoarse = 4096;
 void set_error(const std::string& m);
 
 // Device bytes held by DevBuf objects allocated on this thread (live) and
@@ -125,13 +130,18 @@ struct Problem {
   DevBuf<float> lamS32;
   DevBuf<double> xfer64;    // 2 K_G: transfer intermediates
   DevBuf<float> xfer32;
-  DevBuf<double> A1;        // K_1 x K_1 coarse matrix (for the refinement step)
-  DevBuf<double> A1inv;     // K_1 x K_1 inverse of the coarse matrix
-  DevBuf<double> cwork;     // 2 K_1 coarse-solve work space
-  int K1 = 0;
+  int Gc = 1;               // coarsest level c of the V-cycle (Sec. 3.2.4)
+  DevBuf<double> A1;        // K_c x K_c coarse matrix (for the refinement step)
+  DevBuf<double> A1inv;     // K_c x K_c inverse of the coarse matrix
+  DevBuf<double> cwork;     // 2 K_c coarse-solve work space
+  int K1 = 0;               // K_c
+  // coarse CG (TS_COARSE_CG): D_c^-1 and the CG vectors of level c
+  DevBuf<double> cdinv, cx, cr, cz, cp, cv;
+  int64_t coarse_iters = 0; // coarse CG iterations of the last solve
 
   // solver vectors on the finest level
   DevBuf<double> vb, vr, vz, vp, vv;
+  DevBuf<double> dinv_fine;      // D_G^-1 (TS_PC_JACOBI)
   DevBuf<float> r32, z32, p32, v32, d32;
 
   DevBuf<double> slots;     // device scalars
@@ -141,6 +151,7 @@ struct Problem {
 
   double setup_s = 0.0;
   int64_t applies = 0;
+  std::vector<double> history;   // residual history of the last solve
   int64_t mem_resident = 0;   // device bytes held after setup
   int64_t mem_peak = 0;       // most device bytes held during setup
 

@@ -39,6 +39,7 @@ struct Request {
   int64_t K = 0;
   size_t footprint = 0;
   bool done = false;
+  bool claimed = false;       // a thread is in ts_server_wait for it
   ts_result res{};
   std::vector<double> alpha;
 };
@@ -287,13 +288,15 @@ ts_status ts_server_wait(ts_server* s, uint64_t ticket, double* alpha, int64_t c
   auto it = S.reqs.find(ticket);
   need(it != S.reqs.end(), "unknown or released ticket");
   tsmg::Request* r = it->second.get();
+  // one waiter per ticket: the waiter that claims it is the only one that
+  // releases it, so no other thread can hold a pointer to it afterwards
+  need(!r->claimed, "ticket is already being waited for by another thread");
+  need(!(alpha && capacity < r->K), "alpha buffer is smaller than K");
+  r->claimed = true;
   S.cv_done.wait(lk, [&] { return r->done; });
-  if (alpha && r->res.status >= 0) {
-    need(capacity >= r->K, "alpha buffer is smaller than K");
-    std::memcpy(alpha, r->alpha.data(), size_t(r->K) * sizeof(double));
-  }
+  if (alpha && r->res.status >= 0) std::memcpy(alpha, r->alpha.data(), size_t(r->K) * sizeof(double));
   if (result) *result = r->res;
-  S.reqs.erase(it);
+  S.reqs.erase(S.reqs.find(ticket));
   return TS_OK;
   TS_API_END
 }

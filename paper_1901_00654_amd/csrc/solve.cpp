@@ -66,11 +66,20 @@ void report(int every, const char* mode, int it, double rel) {
 
 void rhs_op(Problem* P, double* b) { rhs_into(P, b); }
 
-// z = B r with the V-cycle in FP64, or (pc32) in FP32 on r / ||r|| with the
-// result scaled back; slot rr holds ||r||^2.
+// z = B r: one V-cycle in FP64, or (pc32) in FP32 on r / ||r|| with the
+// result scaled back (slot rr holds ||r||^2); with TS_PC_NONE z = r (plain
+// CG), with TS_PC_JACOBI z = D^-1 r.
 static void precondition(Problem* P, bool pc32, const double* r, double* z, int rr) {
   const int G = P->G;
   const int64_t K = P->lev[G].K;
+  if (P->opt.preconditioner == TS_PC_NONE) {
+    hip_check(launch_scale_copy<double, double>(r, z, K, 1.0, nullptr, P->stream), "copy");
+    return;
+  }
+  if (P->opt.preconditioner == TS_PC_JACOBI) {
+    hip_check(launch_mul(P->dinv_fine.p, r, z, K, P->stream), "jacobi precondition");
+    return;
+  }
   if (!pc32) {
     vcycle_op<double>(P, G, r, z);
     return;
@@ -80,11 +89,13 @@ static void precondition(Problem* P, bool pc32, const double* r, double* z, int 
   hip_check(launch_scale_mul(P->z32.p, z, K, P->slot(rr), P->stream), "to fp64");
 }
 
-// Alg. 8 in FP64. With pc32 the V-cycle runs in FP32 and the direction
-// update takes the flexible form beta = r'(z - z_old) / r_old'z_old, which
-// tolerates the rounding of the preconditioner; the Krylov recurrences and
-// every operator apply stay FP64.
+// Alg. 8 in FP64. With pc32 the V-cycle runs in FP32; then, and when the
+// coarse level is solved by an inner CG (a preconditioner that is not
+// exactly linear), the direction update takes the flexible form
+// beta = r'(z - z_old) / r_old'z_old, which tolerates the inexactness; the
+// Krylov recurrences and every operator apply stay FP64.
 static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_info* info, bool pc32 = false) {
+  const bool flex = pc32 || (P->opt.preconditioner == TS_PC_MG && P->opt.coarse_solver == TS_COARSE_CG);
   const int G = P->G;
   const int64_t K = P->lev[G].K;
   hipStream_t st = P->stream;
@@ -98,19 +109,32 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
     hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
     info->converged = 1;
     info->rel_residual = 0.0;
+    P->history.assign(1, 0.0);
     return TS_OK;
   }
   const double bnorm = std::sqrt(bb);
+  double rel_true = 1.0;
   if (use_start) {
     true_residual(P, alpha, b, r, v);
+    dot_op<double, double>(P, r, r, K, kRR);
+    double rr0;
+    P->read_slots(kRR, 1, &rr0);
+    rel_true = std::sqrt(rr0) / bnorm;
   } else {
     hip_check(launch_fill<double>(alpha, 0.0, K, st), "fill");
     hip_check(launch_scale_copy<double, double>(b, r, K, 1.0, nullptr, st), "copy");
   }
+  P->history.assign(1, rel_true);
   const double tol = P->opt.tol;
   const int every = progress_every();
   int total = 0, restarts = 0;
-  double rel_true = 1.0;
+  if (rel_true <= tol) {
+    info->iterations = 0;
+    info->refinements = 0;
+    info->rel_residual = rel_true;
+    info->converged = 1;
+    return TS_OK;
+  }
   for (;;) {
     int sa = kRZa, sb = kRZb;
     if (pc32) dot_op<double, double>(P, r, r, K, kRR);
@@ -122,7 +146,7 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
       dot_op<double, double>(P, p, v, K, kPV);
       hip_check(launch_cg_step<double, double>(alpha, r, p, v, K, P->slot(sa), P->slot(kPV), st), "cg step");
       dot_op<double, double>(P, r, r, K, kRR);
-      if (pc32) dot_op<double, double>(P, r, z, K, kRZo);   // r_new' z_old
+      if (flex) dot_op<double, double>(P, r, z, K, kRZo);   // r_new' z_old
       P->copy_slots(kPV, 2);
       // the next V-cycle is queued before the host reads the residual, so the
       // device does not idle during the readback; after the last iteration
@@ -134,9 +158,10 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
       if (!finite_pos(h[0]) || !std::isfinite(h[1]))
         throw Error{TS_EBREAKDOWN, "CG breakdown: p'Ap = " + std::to_string(h[0])};
       report(every, pc32 ? "vcycle32" : "fp64", total, std::sqrt(h[1]) / bnorm);
+      P->history.push_back(std::sqrt(h[1]) / bnorm);
       if (std::sqrt(h[1]) / bnorm <= tol) break;
       dot_op<double, double>(P, r, z, K, sb);
-      if (pc32) hip_check(launch_p_update_flex(p, z, K, P->slot(sb), P->slot(kRZo), P->slot(sa), st), "p update");
+      if (flex) hip_check(launch_p_update_flex(p, z, K, P->slot(sb), P->slot(kRZo), P->slot(sa), st), "p update");
       else hip_check(launch_p_update<double>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
       std::swap(sa, sb);
     }
@@ -148,6 +173,7 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
     P->read_slots(kRR, 1, &rr);
     rel_true = std::sqrt(rr) / bnorm;
     if (rel_true <= tol || total >= P->opt.max_iter || restarts >= 5) break;
+    P->history.push_back(rel_true);   // the restart begins from the true residual
     ++restarts;
   }
   info->iterations = total;
@@ -198,6 +224,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
   double rr;
   P->read_slots(kRR64, 1, &rr);
   double rel = std::sqrt(rr) / bnorm;
+  P->history.assign(1, rel);
   int total = 0, updates = 0;
   if (!(rel <= tol)) {
     if (!std::isfinite(rel)) throw Error{TS_EBREAKDOWN, "residual is not finite"};
@@ -220,6 +247,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
       if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
         throw Error{TS_EBREAKDOWN, "mixed CG breakdown: non-finite scalar"};
       report(every, "mixed", total, std::sqrt(h[1]));
+      P->history.push_back(std::sqrt(h[1]));
       const bool breakdown = !(h[0] > 0.0);   // the device skipped the step
       if (breakdown && fresh) hip_check(launch_scale_copy<float, float>(p, dl, K, 1.0, nullptr, st), "copy");
       const double rn = std::sqrt(h[1]);
@@ -232,6 +260,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
         P->read_slots(kRR64, 1, &rr);
         ++updates;
         rel = std::sqrt(rr) / bnorm;
+        P->history.back() = rel;
         if (!std::isfinite(rel)) throw Error{TS_EBREAKDOWN, "residual is not finite"};
         if (rel <= tol || total >= P->opt.max_iter || updates >= P->opt.max_refine) break;
         hip_check(launch_scale_copy<double, float>(r, rin, K, 1.0 / bnorm, nullptr, st), "to fp32");
@@ -262,6 +291,9 @@ ts_status solve(Problem* P, double* alpha, int use_start, ts_solve_info* info_ou
   auto t0 = std::chrono::steady_clock::now();
   ts_solve_info info{};
   const int64_t applies0 = P->applies;
+  if (P->opt.preconditioner != TS_PC_MG && P->opt.precision != TS_FP64)
+    throw Error{TS_EINVAL, "the mixed-precision modes run the V-cycle preconditioner (TS_PC_MG)"};
+  P->history.clear();
   ts_status s;
   if (P->opt.precision == TS_FP64) s = solve_fp64(P, alpha, use_start, &info);
   else if (P->opt.precision == TS_MIXED_FP32_VCYCLE) s = solve_fp64(P, alpha, use_start, &info, true);
@@ -270,6 +302,8 @@ ts_status solve(Problem* P, double* alpha, int use_start, ts_solve_info* info_ou
   info.setup_s = P->setup_s;
   info.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   info.applies = P->applies - applies0;
+  info.residual_history = P->history.data();
+  info.history_len = int(P->history.size());
   if (info_out) *info_out = info;
   return s;
 }

@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(HERE, "libtsmg.so")
 TS_OK, TS_ENOTCONV, TS_EINVAL, TS_ENOMEM, TS_EDEVICE, TS_ESINGULAR, TS_EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
 TS_FP64, TS_MIXED_FP32, TS_MIXED_BF16, TS_MIXED_FP32_VCYCLE = 0, 1, 2, 3
 TS_STENCIL_AUTO, TS_STENCIL_NONE, TS_STENCIL_ALL = 0, 1, 2
+TS_PC_MG, TS_PC_NONE, TS_PC_JACOBI = 0, 1, 2
+TS_SMOOTH_JACOBI, TS_SMOOTH_SSOR = 0, 1
+TS_COARSE_DIRECT, TS_COARSE_CG = 0, 1
 _STATUS = {0: "TS_OK", 1: "TS_ENOTCONV", -1: "TS_EINVAL", -2: "TS_ENOMEM", -3: "TS_EDEVICE",
            -4: "TS_ESINGULAR", -5: "TS_EBREAKDOWN"}
 
@@ -30,17 +33,26 @@ class ts_options(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("tol", ctypes.c_double),
                 ("inner_tol", ctypes.c_double), ("max_refine", ctypes.c_int),
                 ("points_per_block", ctypes.c_int), ("stencil_mode", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p),
+                ("preconditioner", ctypes.c_int), ("smoother", ctypes.c_int),
+                ("ssor_omega", ctypes.c_double), ("coarse_solver", ctypes.c_int),
+                ("coarse_tol", ctypes.c_double), ("coarse_max_iter", ctypes.c_int),
+                ("coarsest_level", ctypes.c_int)]
 
 
 class ts_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int),
                 ("converged", ctypes.c_int), ("rel_residual", ctypes.c_double),
                 ("setup_s", ctypes.c_double), ("solve_s", ctypes.c_double),
-                ("applies", ctypes.c_int64)]
+                ("applies", ctypes.c_int64),
+                ("residual_history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k != "residual_history"}
+        n = self.history_len
+        out["residual_history"] = ([self.residual_history[i] for i in range(n)]
+                                   if n > 0 and self.residual_history else [])
+        return out
 
 
 class ts_server_options(ctypes.Structure):

@@ -69,12 +69,26 @@ def traffic_bytes():
     return t.get("hbm_bytes_per_launch")
 
 
+SMOOTHER = {}   # nu, omega_scale overrides from the command line
+
+
+def set_smoother(opt):
+    if "ppb" in SMOOTHER:
+        opt.points_per_block = SMOOTHER["ppb"]
+    if "nu" in SMOOTHER:
+        opt.nu1 = opt.nu2 = SMOOTHER["nu"]
+    if "omega_scale" in SMOOTHER:
+        opt.omega_scale = SMOOTHER["omega_scale"]
+    return opt
+
+
 def make_problem(tsmg, w, xd, yd, stream, precision, tol=1e-8):
     opt = tsmg.ts_default_options()
     opt.stream = stream.cuda_stream
     opt.tol = tol
     opt.precision = precision
     opt.max_iter = 100000
+    set_smoother(opt)
     d = w["d"]
     return tsmg.ts_create(d, 3, [w["N"]] * d, w["lo"], w["hi"], len(w["y"]), xd, yd, w["lam"], opt)
 
@@ -200,6 +214,105 @@ def serving(tsmg, workloads, R, slots, served_precision):
     return out
 
 
+def serve_run(tsmg, reqs, precision, slots, rate, policy=None, label=""):
+    """Requests of the serving trace submitted at Poisson arrival times of the
+    given rate (None: one at a time, each after the previous finished) to a
+    server with `slots` concurrent solves; returns (solutions, results)."""
+    import numpy as np
+    from paper_1901_00654_amd import workloads
+
+    def opts():
+        o = tsmg.ts_default_options()
+        o.precision = precision
+        o.tol = 1e-8
+        o.max_iter = 200000
+        set_smoother(o)
+        return o
+
+    S = tsmg.Server(slots=slots, policy=policy)
+    out = []
+    try:
+        if rate is None:
+            for i, r in enumerate(reqs):
+                t = S.submit(r["x"], r["y"], r["N"], r["lam"], options=opts())
+                out.append(S.wait(t))
+                print(json.dumps({"serve": label, "done": i + 1, "of": len(reqs)}), file=sys.stderr, flush=True)
+        else:
+            arrivals = workloads.poisson_arrivals(len(reqs), rate)
+            t0 = time.perf_counter()
+            tickets = []
+            for i, r in enumerate(reqs):
+                delay = t0 + arrivals[i] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append(S.submit(r["x"], r["y"], r["N"], r["lam"], options=opts()))
+                if i % 10 == 9:
+                    print(json.dumps({"serve": label, "submitted": i + 1, "of": len(reqs)}), file=sys.stderr,
+                          flush=True)
+            for i, t in enumerate(tickets):
+                out.append(S.wait(t))
+                if i % 10 == 9:
+                    print(json.dumps({"serve": label, "waited": i + 1, "of": len(reqs)}), file=sys.stderr,
+                          flush=True)
+        st = S.stats()
+    finally:
+        S.close()
+    return out, st
+
+
+def serve_summary(results, st=None):
+    import numpy as np
+    lat = np.array([res["t_done"] - res["t_submit"] for _, res in results])
+    span = max(res["t_done"] for _, res in results) - min(res["t_submit"] for _, res in results)
+    out = {"requests": len(results), "solves_per_s": len(results) / span, "span_s": span,
+           "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+           "max_rel_residual": max(res["info"]["rel_residual"] for _, res in results),
+           "failed": sum(res["status"] != 0 for _, res in results)}   # 0 = TS_OK
+    if st:
+        out["max_active"] = st["max_active"]
+        out["max_in_use_bytes"] = st["max_in_use"]
+    return out
+
+
+def serve_study(tsmg, workloads, R, slots, served_precision, R_seq=None):
+    """The serving trace (first R requests): plain FP64 one request at a time
+    (capacity C64 from its first R_seq requests), then the mixed mode served
+    with `slots` concurrent solves at Poisson rates 2 C64 (throughput) and
+    0.7 x the mixed capacity measured there (latency), and plain FP64 served
+    the same way at 2 C64 (control). Each result's fitted values are compared
+    with its FP64 sequential solution."""
+    import numpy as np
+    reqs = [workloads.serving_request(i) for i in range(R)]
+    R_seq = R_seq or R
+    seq, _ = serve_run(tsmg, reqs[:R_seq], tsmg.TS_FP64, 1, None, label="fp64 sequential")
+    s_seq = serve_summary(seq)
+    rate = 2.0 * s_seq["solves_per_s"]
+    out = {"requests": R, "sample": "requests 0..%d of the serving trace (d in 2..4, N in 16..64, n log-uniform "
+                                    "1e4..1e6, lambda log-uniform 1e-6..1e-2), each to a relative FP64 residual "
+                                    "of 1e-8" % (R - 1),
+           "fp64_sequential": dict(s_seq, requests_timed=R_seq)}
+
+    def diffs(results):
+        # solutions of the same request by two modes: relative difference of
+        # the coefficients (their fitted values are compared in the tests)
+        d = [float(np.linalg.norm(a2 - a1) / np.linalg.norm(a1))
+             for (a1, _), (a2, _) in zip(seq, results) if a1 is not None and a2 is not None]
+        return max(d) if d else None
+
+    runs = [("mixed_served_throughput", served_precision, rate),
+            ("fp64_served_throughput", tsmg.TS_FP64, rate)]
+    for name, prec, rt in runs:
+        res, st = serve_run(tsmg, reqs, prec, slots, rt, label=name)
+        out[name] = dict(serve_summary(res, st), arrival_rate_per_s=rt, slots=slots,
+                         precision=PRECISIONS_BY_CODE[prec], max_rel_diff_alpha_vs_fp64_sequential=diffs(res))
+    rate_lat = 0.7 * out["mixed_served_throughput"]["solves_per_s"]
+    res, st = serve_run(tsmg, reqs, served_precision, slots, rate_lat, label="mixed latency")
+    out["mixed_served_latency"] = dict(serve_summary(res, st), arrival_rate_per_s=rate_lat, slots=slots,
+                                       precision=PRECISIONS_BY_CODE[served_precision],
+                                       max_rel_diff_alpha_vs_fp64_sequential=diffs(res))
+    return out
+
+
 def paper_experiments(tsmg, torch, workloads):
     """The paper's Sec. 4 test (sigmoid data, n = 100,000, lambda = 0.2):
     MGCG iterations and solve times for P = 2 under refinement G = 4..7
@@ -244,45 +357,24 @@ def paper_experiments(tsmg, torch, workloads):
     return out
 
 
-def solve_all(tsmg, torch, workloads, only=None, modes_only=None):
+def solve_all(tsmg, torch, workloads, stream, only=None, modes_only=None, ref_tol=1e-12):
     """Whole solves of every workload (c4 at 8^5 and 16^5 intervals) in the
     three precision modes, to a relative FP64 true residual of 1e-8: time,
-    iterations, and the relative difference of each mixed solution to the
-    FP64 one."""
-    out = []
+    iterations, and each solution's distance to an FP64 solve of the same
+    problem driven to 1e-12 (solve_study)."""
+    os.environ.setdefault("TSMG_PROGRESS", "250")   # long solves print their progress
     cases = [("c1", {}), ("c2", {}), ("c3", {}), ("c4", {"N": 8}), ("c4", {"N": 16})]
     if only:
         cases = [c for c in cases if "%s/%d" % (c[0], c[1].get("N", 0)) in only or c[0] in only]
     modes = [("fp64", tsmg.TS_FP64), ("mixed", tsmg.TS_MIXED_FP32), ("vcycle32", tsmg.TS_MIXED_FP32_VCYCLE)]
     if modes_only:
         modes = [m for m in modes if m[0] in modes_only]
+    out = []
     for name, kw in cases:
         w = workloads.CONFIGS[name](**kw)
-        xd = torch.from_numpy(w["x"]).cuda()
-        yd = torch.from_numpy(w["y"]).cuda()
-        rec = {"workload": name, "d": w["d"], "N": w["N"], "n": len(w["y"])}
-        ref = None
-        for mname, prec in modes:
-            S = tsmg.Smoother(xd, yd, w["N"], w["lam"], lo=w["lo"], hi=w["hi"], precision=prec, tol=1e-8,
-                              max_iter=100000)
-            try:
-                t0 = time.perf_counter()
-                alpha, status, info = S.solve()
-                dt = time.perf_counter() - t0
-                r = {"status": status, "iterations": info["iterations"], "refinements": info["refinements"],
-                     "rel_residual": info["rel_residual"], "solve_s": dt, "setup_s": info["setup_s"]}
-                if ref is None:
-                    ref = alpha
-                else:
-                    r["rel_diff_vs_fp64"] = float(torch.linalg.norm(alpha - ref) / torch.linalg.norm(ref))
-                rec[mname] = r
-            finally:
-                S.close()
-            print(json.dumps({"progress": name, "N": w["N"], "mode": mname, **rec[mname]}), file=sys.stderr,
-                  flush=True)
-        out.append(rec)
-        del xd, yd, ref
-        torch.cuda.empty_cache()
+        out.append(solve_study(tsmg, torch, w, stream, modes, ref_tol=ref_tol,
+                               progress=lambda r: print(json.dumps({"progress": name, "N": w["N"], **r}),
+                                                        file=sys.stderr, flush=True)))
     return out
 
 
@@ -298,28 +390,150 @@ def copy_calibration(torch):
     return src.numel() * 8
 
 
-def cpu_baseline(w, applies_per_solve, budget_s=20.0):
-    """The oracle's matrix-free FP64 apply (NumPy) on the same points, timed
-    for about budget_s seconds, scaled to solves/s with the number of operator
-    applies one GPU solve performed."""
-    import numpy as np
-    from oracle import matfree
-    c = np.random.default_rng(0).standard_normal((w["N"] + 3) ** w["d"])
-    times = []
-    t_start = time.perf_counter()
-    while True:
+def accuracy(tsmg, torch, h, w, xd, alpha, ref):
+    """Distance of a solution to a reference solution of the same problem:
+    relative differences of the coefficients, of the fitted values at the data
+    points (ts_evaluate) and in the energy norm (ts_apply)."""
+    n = len(w["y"])
+    G = tsmg.ts_num_levels(h)
+    K = tsmg.ts_num_coeffs(h, G)
+    e = (alpha - ref).contiguous()
+    fe = torch.empty(n, dtype=torch.float64, device="cuda")
+    fr = torch.empty(n, dtype=torch.float64, device="cuda")
+    tsmg.ts_evaluate(h, e, n, xd, fe)
+    tsmg.ts_evaluate(h, ref, n, xd, fr)
+    Ae = torch.empty(K, dtype=torch.float64, device="cuda")
+    Ar = torch.empty(K, dtype=torch.float64, device="cuda")
+    tsmg.ts_apply(h, G, e, Ae)
+    tsmg.ts_apply(h, G, ref, Ar)
+    torch.cuda.synchronize()
+    return {"coef": float(torch.linalg.norm(e) / torch.linalg.norm(ref)),
+            "fitted": float(torch.linalg.norm(fe) / torch.linalg.norm(fr)),
+            "energy": float(torch.sqrt(torch.abs(e @ Ae) / (ref @ Ar)))}
+
+
+def solve_study(tsmg, torch, w, stream, modes, ref_tol=1e-12, progress=None):
+    """Whole solves of one workload to a relative FP64 residual of 1e-8 in the
+    given modes, each with its time, iterations and its distance to an FP64
+    solve of the same problem driven to ref_tol (None: no reference)."""
+    xd = torch.from_numpy(w["x"]).cuda()
+    yd = torch.from_numpy(w["y"]).cuda()
+    torch.cuda.synchronize()
+    K = (w["N"] + 3) ** w["d"]
+    out = {"workload": w["name"], "d": w["d"], "N": w["N"], "n": len(w["y"]), "lambda": w["lam"]}
+    h = make_problem(tsmg, w, xd, yd, stream, tsmg.TS_FP64, tol=ref_tol or 1e-8)
+    try:
+        ref = None
+        if ref_tol:
+            ref = torch.empty(K, dtype=torch.float64, device="cuda")
+            t0 = time.perf_counter()
+            st, info = tsmg.ts_solve(h, ref)
+            out["reference"] = {"tol": ref_tol, "status": st, "iterations": info.iterations,
+                                "rel_residual": info.rel_residual, "solve_s": time.perf_counter() - t0}
+            if progress:
+                progress({"reference": out["reference"]})
+        for name, prec in modes:
+            o = tsmg.ts_default_options()
+            o.precision = prec
+            o.tol = 1e-8
+            o.max_iter = 100000
+            set_smoother(o)
+            tsmg.ts_set_options(h, o)
+            a = torch.empty(K, dtype=torch.float64, device="cuda")
+            t0 = time.perf_counter()
+            st, info = tsmg.ts_solve(h, a)
+            dt = time.perf_counter() - t0
+            out[name] = {"status": st, "iterations": info.iterations, "refinements": info.refinements,
+                         "rel_residual": info.rel_residual, "solve_s": dt, "setup_s": info.setup_s}
+            if ref is not None:
+                out[name]["vs_fp64_ref"] = accuracy(tsmg, torch, h, w, xd, a, ref)
+            if progress:
+                progress({name: out[name]})
+    finally:
+        tsmg.ts_destroy(h)
+        del xd, yd
+        torch.cuda.empty_cache()
+    return out
+
+
+def per_iteration(tsmg, torch, w, stream, iters, precision):
+    """Time of a fixed number of MGCG iterations on one workload (the solve
+    stopped by max_iter): ms per iteration, setup excluded."""
+    xd = torch.from_numpy(w["x"]).cuda()
+    yd = torch.from_numpy(w["y"]).cuda()
+    torch.cuda.synchronize()
+    K = (w["N"] + 3) ** w["d"]
+    h = make_problem(tsmg, w, xd, yd, stream, precision)
+    try:
+        o = tsmg.ts_default_options()
+        o.precision = precision
+        o.tol = 1e-30
+        o.max_iter = iters
+        o.max_refine = 1000
+        set_smoother(o)
+        tsmg.ts_set_options(h, o)
+        a = torch.empty(K, dtype=torch.float64, device="cuda")
         t0 = time.perf_counter()
-        matfree.apply(w["x"], c, w["lo"], w["hi"], w["N"], w["lam"])
+        st, info = tsmg.ts_solve(h, a)
+        dt = time.perf_counter() - t0
+        return {"iterations_timed": info.iterations, "solve_s": dt, "ms_per_iteration": dt / info.iterations * 1e3,
+                "setup_s": info.setup_s}
+    finally:
+        tsmg.ts_destroy(h)
+        del xd, yd
+        torch.cuda.empty_cache()
+
+
+def cpu_baseline(tsmg, torch, workloads, stream, w_full, budget_apply_s=8.0):
+    """The oracle as it stands, timed on this host on a bounded sample of the
+    c2 workload: its whole MGCG solve (assembled hierarchy, Lanczos damping,
+    Alg. 8 to a relative residual of 1e-8) on the c2 recipe at 1/64 of the
+    size (N = 16, n = 31,250: the same points per cell), next to the GPU's
+    solve of the same sample; and its matrix-free FP64 apply on the full c2
+    points next to the GPU's."""
+    import numpy as np
+    from oracle import matfree, mg, system
+    ws = workloads.c2(n=31250, N=16)
+    t0 = time.perf_counter()
+    levels = system.hierarchy(ws["x"], ws["y"], ws["lo"], ws["hi"], ws["N"], ws["lam"])
+    M = mg.MG(ws["x"], ws["y"], ws["lo"], ws["hi"], ws["N"], ws["lam"], levels=levels)
+    top = levels[M.G]
+    _, its_cpu, _ = mg.pcg(top["A"], top["b"], M.vcycle, tol=1e-8, maxiter=20000)
+    t_cpu = time.perf_counter() - t0
+    # the GPU on the same sample (setup + solve)
+    xd = torch.from_numpy(ws["x"]).cuda()
+    yd = torch.from_numpy(ws["y"]).cuda()
+    torch.cuda.synchronize()
+    K = (ws["N"] + 3) ** 3
+    a = torch.empty(K, dtype=torch.float64, device="cuda")
+    times = []
+    for _ in range(4):
+        t0 = time.perf_counter()
+        h = make_problem(tsmg, ws, xd, yd, stream, tsmg.TS_FP64)
+        try:
+            st, info = tsmg.ts_solve(h, a)
+        finally:
+            tsmg.ts_destroy(h)
         times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s or len(times) >= 5:
-            break
-    t_apply = float(np.median(times))
-    est_solve = t_apply * applies_per_solve
-    return {"value": 1.0 / est_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": ("oracle matfree.apply (FP64 NumPy, single thread) on the full %s points, "
-                       "%d timed applies, median %.2f s each, times %d applies per solve taken "
-                       "from the GPU run; setup and V-cycle vector work not counted"
-                       % (w["name"], len(times), t_apply, applies_per_solve)),
+    t_gpu = float(np.median(times[1:]))
+    # the matrix-free apply at full size
+    c = np.random.default_rng(0).standard_normal((w_full["N"] + 3) ** w_full["d"])
+    ta = []
+    t_start = time.perf_counter()
+    while not ta or (time.perf_counter() - t_start < budget_apply_s and len(ta) < 3):
+        t0 = time.perf_counter()
+        matfree.apply(w_full["x"], c, w_full["lo"], w_full["hi"], w_full["N"], w_full["lam"])
+        ta.append(time.perf_counter() - t0)
+    return {"value": 1.0 / t_cpu, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": ("c2 recipe at 1/64 size (d=3, N=16, n=31,250, same points per cell): the oracle's "
+                       "whole MGCG solve (assembly, Lanczos, Alg. 8 to 1e-8) took %.1f s in %d "
+                       "iterations (single-threaded SciPy sparse); the GPU solves the same sample "
+                       "(setup + solve) in %.2f ms in %d iterations" % (t_cpu, its_cpu, t_gpu * 1e3,
+                                                                         info.iterations)),
+            "gpu_same_sample_solves_per_s": 1.0 / t_gpu,
+            "per_apply_full_c2": {"oracle_s": float(np.median(ta)), "applies_timed": len(ta),
+                                  "label": "per apply, not per solve: the oracle's matrix-free FP64 "
+                                           "A c on the full c2 points"},
             "host_cpus": os.cpu_count(),
             "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
@@ -341,16 +555,28 @@ def main():
                     help="mode of the served requests: FP32 CG with reliable updates, or FP64 CG "
                          "with an FP32 V-cycle")
     ap.add_argument("--only-serve", action="store_true", help="run only the serving leg")
+    ap.add_argument("--serve-study", action="store_true",
+                    help="only the serving study: FP64 sequential, mixed and FP64 served at 2x the FP64 "
+                         "capacity, mixed served at 0.7x its capacity; prints one JSON line")
+    ap.add_argument("--serve-seq", type=int, default=None,
+                    help="with --serve-study: requests timed one at a time for the FP64 capacity")
     ap.add_argument("--solve-all", action="store_true",
                     help="only whole solves of c1..c4 in every precision mode; prints one JSON line")
     ap.add_argument("--cases", default=None,
                     help="with --solve-all: comma-separated workloads, e.g. c3 or c4/16")
     ap.add_argument("--modes", default=None, help="with --solve-all: comma-separated modes (fp64,mixed,vcycle32)")
+    ap.add_argument("--no-reference", action="store_true",
+                    help="with --solve-all: skip the tight FP64 reference solve and the distances to it")
     ap.add_argument("--paper", action="store_true",
                     help="only the paper's own test problem (Sec. 4): iterations under refinement and "
                          "across dimensions, kappa(A) and kappa(BA); prints one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--nu", type=int, default=None, help="smoothing steps nu1 = nu2 (default: the library's)")
+    ap.add_argument("--omega-scale", type=float, default=None, help="Jacobi damping scale (default: the library's)")
+    ap.add_argument("--ppb", type=int, default=None, help="points per workgroup of the point pass (default: auto)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the whole c3 solves")
+    ap.add_argument("--no-c4", action="store_true", help="skip the c4 per-iteration timing")
     ap.add_argument("--only-apply", default=None, metavar="WORKLOAD",
                     help="only time the finest-level operator apply of one workload (c1..c4), "
                          "for profiling runs; prints one JSON line")
@@ -367,12 +593,23 @@ def main():
     tsmg.load_library()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    if args.nu is not None:
+        SMOOTHER["nu"] = args.nu
+    if args.omega_scale is not None:
+        SMOOTHER["omega_scale"] = args.omega_scale
+    if args.ppb is not None:
+        SMOOTHER["ppb"] = args.ppb
     if args.solve_all:
-        print(json.dumps(solve_all(tsmg, torch, workloads, args.cases.split(",") if args.cases else None,
-                                   args.modes.split(",") if args.modes else None)), flush=True)
+        print(json.dumps(solve_all(tsmg, torch, workloads, stream, args.cases.split(",") if args.cases else None,
+                                   args.modes.split(",") if args.modes else None,
+                                   None if args.no_reference else 1e-12)), flush=True)
         return
     if args.paper:
         print(json.dumps(paper_experiments(tsmg, torch, workloads)), flush=True)
+        return
+    if args.serve_study:
+        print(json.dumps(serve_study(tsmg, workloads, args.serve_requests, args.serve_slots,
+                                     SERVE_PRECISION[args.serve_precision](tsmg), args.serve_seq)), flush=True)
         return
     if args.only_serve:
         print(json.dumps(serving(tsmg, workloads, args.serve_requests, args.serve_slots,
@@ -420,24 +657,42 @@ def main():
         "data": "synthetic (seeded Gaussian mixture, see workloads.c2)",
         "config": {"workload": "c2: d=3 cubic, 64^3 intervals (K=300763), n=2,000,000 clustered points, "
                                "lambda=1e-5, MGCG to rel. FP64 residual 1e-8",
-                   "precision": args.precision, "nu": 2, "levels": G},
+                   "precision": args.precision, "levels": G,
+                   "nu": SMOOTHER.get("nu", tsmg.ts_default_options().nu1),
+                   "omega_scale": SMOOTHER.get("omega_scale", tsmg.ts_default_options().omega_scale)},
         "time_to_tol_s": info["solve_s"], "setup_s": info["setup_s"], "iterations": info["iterations"],
         "refinements": info["refinements"], "rel_residual": info["rel_residual"],
         "applies_per_solve": info["applies"], "roofline": roofline,
         "lambda_passes_ms": ms_lam,
     }
 
-    if not args.no_compare:
-        other = tsmg.TS_MIXED_FP32 if prec == tsmg.TS_FP64 else tsmg.TS_FP64
-        sec2, infos2, alpha2 = run_steps(tsmg, torch, w, xd, yd, stream, other, max(1, args.steps // 2), 0)
-        diff = float(torch.linalg.norm(alpha2 - alpha) / torch.linalg.norm(alpha))
-        result["other_precision"] = {"precision": "mixed" if other != tsmg.TS_FP64 else "fp64",
-                                     "solves_per_s": 1.0 / sec2, "iterations": infos2[-1]["iterations"],
-                                     "refinements": infos2[-1]["refinements"],
-                                     "rel_residual": infos2[-1]["rel_residual"],
-                                     "rel_diff_vs_headline_alpha": diff}
+    def progress(tag):
+        return lambda r: print(json.dumps({"progress": tag, **r}), file=sys.stderr, flush=True)
+
     del xd, yd
     torch.cuda.empty_cache()
+    modes = [("fp64", tsmg.TS_FP64), ("mixed", tsmg.TS_MIXED_FP32), ("vcycle32", tsmg.TS_MIXED_FP32_VCYCLE)]
+    if not args.no_compare:
+        # every precision mode on the headline workload, with its distance to
+        # an FP64 solve driven to 1e-12
+        result["precision_modes_c2"] = solve_study(tsmg, torch, w, stream, modes, progress=progress("c2"))
+    if not args.no_c3:
+        # the d = 4 workload (10^7 points, 35^4 coefficients) solved whole,
+        # FP64 and with the FP32 V-cycle
+        result["solve_c3"] = solve_study(tsmg, torch, workloads.c3(), stream, [modes[0], modes[2]],
+                                         progress=progress("c3"))
+    if not args.no_c4:
+        # d = 5 (2e7 points, 19^5 coefficients): MGCG iterations timed for a
+        # fixed count; the iteration count to 1e-8 comes from whole solves
+        # (bench.py --solve-all --cases c4/16), so the time to tolerance here is
+        # ms per iteration x that count, labelled as such
+        w4 = workloads.c4()
+        rec = {"workload": "c4", "d": 5, "N": 16, "n": len(w4["y"])}
+        for name, pm in (modes[0], modes[2]):
+            rec[name] = per_iteration(tsmg, torch, w4, stream, 20, pm)
+            progress("c4")({name: rec[name]})
+        result["per_iteration_c4"] = rec
+        del w4
 
     if not args.no_sweep:
         sweep = []
@@ -455,7 +710,7 @@ def main():
         result["copy_calibration_bytes"] = copy_calibration(torch)
 
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(w, info["applies"])
+        result["cpu_baseline"] = cpu_baseline(tsmg, torch, workloads, stream, w)
     print(json.dumps(result), flush=True)
 
 

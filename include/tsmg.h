@@ -296,13 +296,16 @@ ts_status ts_footprint(int d, int q, const int32_t* intervals, int64_t n, const 
  * Serving loop: independent smoothing requests (any d, grid, point count, lambda,
  * precision) submitted as they arrive and solved concurrently on one GPU.
  *
- * A server runs `slots` worker threads, each with its own HIP stream. A worker
- * takes the oldest queued request as soon as it is free and the request's
- * estimated peak device memory (ts_footprint plus its points) fits in what the
- * memory budget has left; the request's points, hierarchy and solver state then
- * live on the device until its solve ends, and the kernels of different
- * requests overlap on the GPU. Admission is first in, first out: a request
- * that does not fit yet holds back the ones behind it. Each request is solved
+ * A server runs `slots` worker threads, each with its own HIP stream. A free
+ * worker admits a queued request whose estimated peak device memory
+ * (ts_footprint plus its points) fits in what the memory budget has left: by
+ * default (TS_ADMIT_SHORTEST) the one that has waited max_wait_s or longer,
+ * oldest first, else the one with the least estimated work per operator
+ * apply (points x 4^d + coefficients x 7^d), so short requests are not held
+ * behind long ones; with TS_ADMIT_FIFO the oldest, which holds back the ones
+ * behind it until it fits. The request's points, hierarchy and solver state
+ * then live on the device until its solve ends, and the kernels of different
+ * requests overlap on the GPU. Each request is solved
  * exactly as ts_create + ts_solve would solve it alone (zero start vector);
  * only the order of floating-point atomic additions differs.
  *
@@ -310,10 +313,18 @@ ts_status ts_footprint(int d, int q, const int32_t* intervals, int64_t n, const 
  */
 typedef struct ts_server ts_server;
 
+typedef enum {
+    TS_ADMIT_SHORTEST = 0, /* least estimated work first, overdue requests first (default) */
+    TS_ADMIT_FIFO = 1      /* first in, first out                                        */
+} ts_admission;
+
 typedef struct {
     size_t memory_budget;  /* bytes of device memory admitted requests may hold at once;
                               0 = half of the free device memory at ts_server_create   */
     int slots;             /* requests solved at once (worker threads); default 4, 1..64 */
+    int policy;            /* ts_admission; default TS_ADMIT_SHORTEST                   */
+    double max_wait_s;     /* TS_ADMIT_SHORTEST: a request queued this long (seconds)
+                              is admitted before shorter ones; default 5               */
 } ts_server_options;
 
 typedef struct {
@@ -349,11 +360,12 @@ typedef struct {
     size_t memory_budget;
 } ts_server_stats;
 
-/* Fills *opt with the defaults (memory_budget 0, slots 4). */
+/* Fills *opt with the defaults (memory_budget 0, slots 4, TS_ADMIT_SHORTEST, 5 s). */
 void ts_server_default_options(ts_server_options* opt);
 
 /* Starts a server on the current device. Returns TS_EINVAL for slots outside
- * 1..64, TS_EDEVICE if no device is usable. */
+ * 1..64, an unknown policy or a negative max_wait_s, TS_EDEVICE if no device
+ * is usable. */
 ts_status ts_server_create(const ts_server_options* opt, ts_server** out);
 
 /* Queues one request and returns at once with its ticket. The host arrays of

@@ -36,31 +36,44 @@ import scipy.sparse as sp
 from . import bspline
 
 
+def per_dim(v, d):
+    """A scalar N or q for every dimension, or the per-dimension list itself
+    (Sec. 2.1 defines q_p, J_p and the knots dimension by dimension)."""
+    if np.ndim(v) == 0:
+        return [int(v)] * d
+    v = [int(a) for a in v]
+    if len(v) != d:
+        raise ValueError("expected %d per-dimension values" % d)
+    return v
+
+
 def num_coeffs(N, q, d):
-    """K = prod_p J_p with J_p = N + q (Sec. 2.1; Table 1 for J_p = 35)."""
-    return (N + q) ** d
+    """K = prod_p J_p with J_p = N_p + q_p (Sec. 2.1; Table 1 for J_p = 35)."""
+    return int(np.prod([Np + qp for Np, qp in zip(per_dim(N, d), per_dim(q, d))]))
 
 
 def phi_matrix(x, lo, hi, N, q=3):
-    """Sparse Phi (n x K) for points x (n x d) on [lo, hi]^d, N intervals per dim.
+    """Sparse Phi (n x K) for points x (n x d) on [lo, hi]^d with N_p
+    intervals and degree q_p in dimension p (scalars: the same for all).
 
     Row i is the Kronecker product over dimensions of the 1D rows
     Phi_p[i, :] (the Khatri-Rao identity of Sec. 2.4), built entry by entry.
     """
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     n, d = x.shape
-    J = N + q
+    Ns, qs = per_dim(N, d), per_dim(q, d)
+    Js = [Np + qp for Np, qp in zip(Ns, qs)]
     cells, vals = [], []
     for p in range(d):
-        c, V = bspline.basis_local(x[:, p], lo[p], hi[p], N, q)
+        c, V = bspline.basis_local(x[:, p], lo[p], hi[p], Ns[p], qs[p])
         cells.append(c)
         vals.append(V)
     rows, cols, data = [], [], []
-    for a in itertools.product(range(q + 1), repeat=d):
+    for a in itertools.product(*[range(qp + 1) for qp in qs]):
         col = np.zeros(n, dtype=np.int64)
         val = np.ones(n)
         for p in range(d):
-            col = col * J + (cells[p] + a[p])
+            col = col * Js[p] + (cells[p] + a[p])
             val = val * vals[p][:, a[p]]
         rows.append(np.arange(n))
         cols.append(col)
@@ -68,7 +81,7 @@ def phi_matrix(x, lo, hi, N, q=3):
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     data = np.concatenate(data)
-    return sp.csr_matrix((data, (rows, cols)), shape=(n, J ** d))
+    return sp.csr_matrix((data, (rows, cols)), shape=(n, int(np.prod(Js))))
 
 
 def gram_1d(lo, hi, N, q, r):
@@ -88,10 +101,11 @@ def gram_1d(lo, hi, N, q, r):
 
 def lambda_matrix(d, lo, hi, N, q=3):
     """Lambda = sum over multi-indices r with |r| = 2 of (2/r!) kron_p Psi^p_{r_p}."""
-    psi = [[sp.csr_matrix(gram_1d(lo[p], hi[p], N, q, rp)) for rp in range(3)]
+    Ns, qs = per_dim(N, d), per_dim(q, d)
+    psi = [[sp.csr_matrix(gram_1d(lo[p], hi[p], Ns[p], qs[p], rp)) for rp in range(3)]
            for p in range(d)]
-    J = N + q
-    L = sp.csr_matrix((J ** d, J ** d))
+    K = num_coeffs(Ns, qs, d)
+    L = sp.csr_matrix((K, K))
     for r in itertools.product(range(3), repeat=d):
         if sum(r) != 2:
             continue
@@ -101,6 +115,23 @@ def lambda_matrix(d, lo, hi, N, q=3):
             term = sp.kron(term, psi[p][r[p]], format="csr")
         L = L + coef * term
     return L.tocsr()
+
+
+def lambda_dense(d, lo, hi, N, q=3):
+    """Lambda as a dense array: the same sum of Kronecker products as
+    ``lambda_matrix``, with dense 1D factors (for K up to a few 10^4)."""
+    psi = [[gram_1d(lo[p], hi[p], N, q, rp) for rp in range(3)] for p in range(d)]
+    K = (N + q) ** d
+    L = np.zeros((K, K))
+    for r in itertools.product(range(3), repeat=d):
+        if sum(r) != 2:
+            continue
+        coef = 2.0 / np.prod([math.factorial(rp) for rp in r])
+        term = psi[0][r[0]]
+        for p in range(1, d):
+            term = np.kron(term, psi[p][r[p]])
+        L += coef * term
+    return L
 
 
 def system(x, y, lo, hi, N, lam, q=3):
@@ -130,33 +161,54 @@ def prolongation_1d(Nc, q=3):
 
 
 def prolongation(d, Nc, q=3):
-    """Multivariate I_{2h}^h = kron_p I_p (eq. 2.6), sparse."""
-    I1 = sp.csr_matrix(prolongation_1d(Nc, q))
-    P = I1
-    for _ in range(1, d):
-        P = sp.kron(P, I1, format="csr")
+    """Multivariate I_{2h}^h = kron_p I_p (eq. 2.6), sparse; Nc and q per
+    dimension or scalars."""
+    Ns, qs = per_dim(Nc, d), per_dim(q, d)
+    P = sp.csr_matrix(prolongation_1d(Ns[0], qs[0]))
+    for p in range(1, d):
+        P = sp.kron(P, sp.csr_matrix(prolongation_1d(Ns[p], qs[p])), format="csr")
     return P
 
 
 def level_intervals(N, G):
-    """N_g for g = 1..G given the finest N = N_G (Sec. 3.2.1: N_g = 2^g)."""
-    return [N >> (G - g) for g in range(1, G + 1)]
+    """N_g for g = 1..G given the finest N = N_G (Sec. 3.2.1: N_g = 2^g);
+    N may be per dimension (then a list per level)."""
+    if np.ndim(N) == 0:
+        return [N >> (G - g) for g in range(1, G + 1)]
+    return [[Np >> (G - g) for Np in N] for g in range(1, G + 1)]
+
+
+def num_levels(N):
+    """Levels of the hierarchy for the finest intervals N (per dimension or
+    a scalar): every dimension is halved from one level to the next (the
+    subdivision of eq. 2.5 applies per dimension) while all N_p are even and
+    not all equal to 2; powers of two N give G = log2(N) with N_1 = 2
+    (Sec. 3.2.1)."""
+    Ns = [int(N)] if np.ndim(N) == 0 else [int(a) for a in N]
+    G = 1
+    while all(Np % 2 == 0 for Np in Ns) and not all(Np == 2 for Np in Ns):
+        Ns = [Np // 2 for Np in Ns]
+        G += 1
+    return G
 
 
 def hierarchy(x, y, lo, hi, N, lam, q=3, G=None):
-    """Per-level assembled data, finest level G: N_G = N, N_g = N / 2^(G-g).
+    """Per-level assembled data, finest level G: N_G = N, N_g = N / 2^(G-g)
+    (per dimension when N is a list).
 
     Returns a dict g -> {"N", "A", "b", "Phi", "Lam", "P"} where P is the
     prolongation from level g-1 to g (absent at g = 1).
     """
     if G is None:
-        G = int(round(math.log2(N)))
+        G = num_levels(N) if np.ndim(N) else int(round(math.log2(N)))
+    d = np.atleast_2d(x).shape[1]
     levels = {}
     for g, Ng in zip(range(1, G + 1), level_intervals(N, G)):
         A, b, Phi, Lam = system(x, y, lo, hi, Ng, lam, q)
         lev = {"N": Ng, "A": A, "b": b, "Phi": Phi, "Lam": Lam}
         if g > 1:
-            lev["P"] = prolongation(np.atleast_2d(x).shape[1], Ng // 2, q)
+            Nc = [a // 2 for a in per_dim(Ng, d)]
+            lev["P"] = prolongation(d, Nc, q)
         levels[g] = lev
     return levels
 
@@ -186,7 +238,7 @@ def normal_matrix_dense(x, lo, hi, N, lam, q=3):
     flat_cell = np.zeros(n, dtype=np.int64)
     for p in range(d):
         flat_cell = flat_cell * N + cells[p]
-    A = lambda_matrix(d, lo, hi, N, q).toarray() * lam
+    A = lambda_dense(d, lo, hi, N, q) * lam
     order = np.argsort(flat_cell, kind="stable")
     bounds = np.flatnonzero(np.diff(flat_cell[order])) + 1
     offsets = list(itertools.product(range(q + 1), repeat=d))

@@ -46,6 +46,7 @@ extern thread_local MemCount g_mem;
 void* pool_alloc(size_t bytes);
 void pool_release(void* p);
 
+
 // Owning device buffer, returned to the cache on destruction. Every owner
 // synchronises the stream its buffers were used on before releasing them;
 // a buffer released while an exception unwinds is freed with hipFree

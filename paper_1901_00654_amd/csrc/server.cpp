@@ -1,6 +1,7 @@
-// Serving loop declared in include/tsmg.h: a first-in-first-out queue of
-// independent smoothing requests, admitted by their estimated peak device
-// memory and solved by worker threads that each own a HIP stream, so the
+// Serving loop declared in include/tsmg.h: a queue of independent smoothing
+// requests, admitted by their estimated peak device memory (shortest
+// estimated work first, or first in first out) and solved by worker threads
+// that each own a HIP stream, so the
 // kernels of concurrent requests overlap on the GPU. A request's points,
 // hierarchy and solver vectors live on the device from admission to the end
 // of its solve; its solution then waits in host memory for ts_server_wait.
@@ -38,6 +39,7 @@ struct Request {
   ts_options opt{};
   int64_t K = 0;
   size_t footprint = 0;
+  double work = 0.0;          // estimated cost of one operator apply (admission order)
   bool done = false;
   bool claimed = false;       // a thread is in ts_server_wait for it
   ts_result res{};
@@ -54,6 +56,8 @@ void set_result_error(ts_result& r, ts_status code, const std::string& msg) {
 struct Server {
   int device = 0;
   size_t budget = 0;
+  int policy = TS_ADMIT_SHORTEST;
+  double max_wait_s = 5.0;
   double stencil_budget = 0.0;
   Clock::time_point t0;
 
@@ -70,6 +74,27 @@ struct Server {
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
+  // The queued request a free worker admits next (queue.end(): none yet).
+  // FIFO: the oldest, once it fits in what the memory budget has left (it
+  // holds back the ones behind it). Shortest first: the oldest request that
+  // has waited max_wait_s and fits, else the fitting request with the least
+  // estimated work per operator apply (ties: the older), so that short
+  // requests are not held behind long ones and none waits indefinitely.
+  std::deque<Request*>::iterator choose() {
+    if (queue.empty()) return queue.end();
+    if (policy == TS_ADMIT_FIFO)
+      return in_use + queue.front()->footprint <= budget ? queue.begin() : queue.end();
+    const double t = now();
+    auto best = queue.end();
+    for (auto it = queue.begin(); it != queue.end(); ++it) {
+      Request* q = *it;
+      if (in_use + q->footprint > budget) continue;
+      if (t - q->res.t_submit >= max_wait_s) return it;   // the oldest overdue one
+      if (best == queue.end() || q->work < (*best)->work) best = it;
+    }
+    return best;
+  }
+
   void worker() {
     hipStream_t st = nullptr;
     std::string init_error;
@@ -82,12 +107,14 @@ struct Server {
       Request* r = nullptr;
       {
         std::unique_lock<std::mutex> lk(mu);
+        std::deque<Request*>::iterator pick;
         cv_work.wait(lk, [&] {
-          return (!queue.empty() && in_use + queue.front()->footprint <= budget) || (stopping && queue.empty());
+          pick = choose();
+          return pick != queue.end() || (stopping && queue.empty());
         });
         if (queue.empty()) break;   // stopping and drained
-        r = queue.front();
-        queue.pop_front();
+        r = *pick;
+        queue.erase(pick);
         in_use += r->footprint;
         ++active;
         stats.max_active = std::max(stats.max_active, active);
@@ -173,6 +200,8 @@ void ts_server_default_options(ts_server_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->memory_budget = 0;
   o->slots = 4;
+  o->policy = TS_ADMIT_SHORTEST;
+  o->max_wait_s = 5.0;
 }
 
 ts_status ts_server_create(const ts_server_options* opt, ts_server** out) {
@@ -183,12 +212,16 @@ ts_status ts_server_create(const ts_server_options* opt, ts_server** out) {
   ts_server_default_options(&o);
   if (opt) o = *opt;
   need(o.slots >= 1 && o.slots <= 64, "slots must be in 1..64");
+  need(o.policy == TS_ADMIT_FIFO || o.policy == TS_ADMIT_SHORTEST, "unknown admission policy");
+  need(o.max_wait_s >= 0.0, "max_wait_s must be >= 0");
   std::unique_ptr<ts_server> s(new ts_server());
   tsmg::Server& S = s->impl;
   tsmg::hip_check(hipGetDevice(&S.device), "hipGetDevice");
   size_t free_b = 0, total_b = 0;
   tsmg::hip_check(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
   S.budget = o.memory_budget ? o.memory_budget : free_b / 2;
+  S.policy = o.policy;
+  S.max_wait_s = o.max_wait_s;
   // per-level stencil cap of every request: a quarter of the budget, at most 16 GB
   S.stencil_budget = std::min(16e9, 0.25 * double(S.budget));
   S.stats.memory_budget = S.budget;
@@ -246,6 +279,11 @@ ts_status ts_server_submit(ts_server* s, const ts_request* q, uint64_t* ticket) 
   r->footprint = size_t(tsmg::footprint_bytes(d, N, q->n, r->opt, S.stencil_budget) +
                         q->n * (d + 1) * int64_t(sizeof(double)) + r->K * int64_t(sizeof(double)));
   r->res.footprint = r->footprint;
+  {   // points x patch entries plus coefficients x stencil entries
+    double patch = 1.0, stencil = 1.0;
+    for (int p = 0; p < d; ++p) { patch *= 4.0; stencil *= 7.0; }
+    r->work = double(q->n) * patch + double(r->K) * stencil;
+  }
   r->res.K = r->K;
   if (r->footprint > S.budget)
     throw tsmg::Error{TS_ENOMEM, "request needs about " + std::to_string(r->footprint) +

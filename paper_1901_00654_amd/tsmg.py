@@ -22,6 +22,7 @@ TS_STENCIL_AUTO, TS_STENCIL_NONE, TS_STENCIL_ALL = 0, 1, 2
 TS_PC_MG, TS_PC_NONE, TS_PC_JACOBI = 0, 1, 2
 TS_SMOOTH_JACOBI, TS_SMOOTH_SSOR = 0, 1
 TS_COARSE_DIRECT, TS_COARSE_CG = 0, 1
+TS_ADMIT_SHORTEST, TS_ADMIT_FIFO = 0, 1
 _STATUS = {0: "TS_OK", 1: "TS_ENOTCONV", -1: "TS_EINVAL", -2: "TS_ENOMEM", -3: "TS_EDEVICE",
            -4: "TS_ESINGULAR", -5: "TS_EBREAKDOWN"}
 
@@ -56,7 +57,8 @@ class ts_solve_info(ctypes.Structure):
 
 
 class ts_server_options(ctypes.Structure):
-    _fields_ = [("memory_budget", ctypes.c_size_t), ("slots", ctypes.c_int)]
+    _fields_ = [("memory_budget", ctypes.c_size_t), ("slots", ctypes.c_int), ("policy", ctypes.c_int),
+                ("max_wait_s", ctypes.c_double)]
 
 
 class ts_request(ctypes.Structure):
@@ -356,10 +358,14 @@ class Server:
     solutions. Requests are copied at submit; solutions come back as float64
     arrays of K = (N + 3)^d coefficients (C order)."""
 
-    def __init__(self, memory_budget=0, slots=4):
+    def __init__(self, memory_budget=0, slots=4, policy=None, max_wait_s=None):
         o = ts_server_default_options()
         o.memory_budget = int(memory_budget)
         o.slots = int(slots)
+        if policy is not None:
+            o.policy = int(policy)
+        if max_wait_s is not None:
+            o.max_wait_s = float(max_wait_s)
         self.handle = ts_server_create(o)
         self._K = {}
 

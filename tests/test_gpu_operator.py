@@ -134,17 +134,24 @@ def test_transfer_every_level(prob):
 
 
 def test_coarse_solve(prob):
+    """Sec. 3.2.4. Two FP64 solves of A_1 x = b agree only to about
+    kappa(A_1) eps, and kappa(A_1) reaches 1e16 here at d = 5 (the five
+    B-splines of a two-interval grid are nearly dependent on the box). The
+    check is the normwise backward error, which a backward-stable FP64
+    solver keeps near eps whatever the conditioning; the forward differences
+    are printed."""
     w, S = prob
     A1, _, _ = gc.level_matrix(w, w["N"] >> (S.G - 1))
     A1 = A1.toarray()
     b = np.random.default_rng(103).standard_normal(S.K(1))
     ref = np.linalg.solve(A1, b)
     x = S.coarse_solve(b).cpu().numpy()
-    kappa = np.linalg.cond(A1)
-    # two FP64 solvers agree to the conditioning of A_1 (it reaches 1e7 and
-    # more for small lambda at d >= 3)
-    assert np.linalg.norm(x - ref) <= max(1e-12, 1e-13 * kappa) * np.linalg.norm(ref)
-    assert np.linalg.norm(A1 @ x - b) <= 1e-13 * kappa * np.linalg.norm(b)
+    back = np.linalg.norm(A1 @ x - b) / (np.linalg.norm(A1, 2) * np.linalg.norm(x) + np.linalg.norm(b))
+    e = x - ref
+    energy = np.sqrt(abs(e @ A1 @ e) / (ref @ A1 @ ref))
+    print("coarse solve: backward error %.2e, energy-norm difference %.2e, kappa(A_1) %.1e"
+          % (back, energy, np.linalg.cond(A1)), flush=True)
+    assert back <= 1e-14
 
 
 def test_evaluate(prob):
@@ -158,3 +165,66 @@ def test_evaluate(prob):
     yq = S.evaluate(torch.as_tensor(alpha).cuda(), xq).cpu().numpy()
     ref = system.evaluate(alpha, xq, w["lo"], w["hi"], w["N"])
     assert gc.rel(yq, ref) < 1e-13
+
+
+def _on_knots_case(d, N, n, seed):
+    """Uniform points with a third of the coordinates moved exactly onto knots
+    lo + j h (j = 0..N, so also onto hi), where the cell index switches."""
+    w = gc.uniform_case(d, n, N, 1e-2, seed)
+    rng = np.random.default_rng(seed + 100)
+    x = w["x"].copy()
+    for p in range(d):
+        pick = rng.random(n) < 1.0 / 3.0
+        j = rng.integers(0, N + 1, size=n)
+        h = (w["hi"][p] - w["lo"][p]) / N
+        knots = np.where(j == N, w["hi"][p], w["lo"][p] + j * h)
+        x[pick, p] = knots[pick]
+    w["x"] = x
+    return w
+
+
+@pytest.mark.parametrize("d,N", [(2, 16), (3, 8), (5, 4)])
+def test_apply_points_on_knots_and_hi(lib, d, N):
+    """Points exactly on interior knots and on the upper bound hi (reading
+    R12: cell = min(floor((x - lo) / h), N - 1)) on every level: A_g c, Phi'y,
+    diag(A_g) and the fit at those points, against the oracle."""
+    w = _on_knots_case(d, N, 3001 if d < 5 else 4001, 40 + d)
+    assert np.any(w["x"] == np.asarray(w["hi"])[None, :])
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"])
+    try:
+        rng = np.random.default_rng(107)
+        for g in levels(S):
+            Ng = w["N"] >> (S.G - g)
+            c = rng.standard_normal(S.K(g))
+            assert gc.rel(S.apply(g, c).cpu().numpy(), gc.oracle_apply(w, Ng, c)) < 1e-12, g
+            assert gc.rel(S.diag(g).cpu().numpy(), gc.oracle_diag(w, Ng)) < 1e-12, g
+        b = matfree.rhs(w["x"], w["y"], w["lo"], w["hi"], w["N"])
+        assert gc.rel(S.rhs().cpu().numpy(), b) < 1e-12
+        alpha = rng.standard_normal(S.K())
+        yq = S.evaluate(S._dev(alpha, S.torch.float64), w["x"]).cpu().numpy()
+        ref = matfree.evaluate(alpha, w["x"], w["lo"], w["hi"], w["N"])
+        assert gc.rel(yq, ref) < 1e-13
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("recipe,n,N", [("c3", 60013, 8), ("c4", 40009, 4)])
+def test_apply_fullsize_layout(lib, recipe, n, N):
+    """The work split the full workloads take: 512 points per workgroup with
+    the packed work lists of d >= 4, and for the c4 recipe the corner cluster
+    (most of 8,000 points in one cell of N = 4), whose tile is cut into
+    several chunks. Every entry of A_G c, Phi'y and diag(A_G) is compared."""
+    w = gc.case(recipe, n, N)
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"], points_per_block=512,
+                      stencil_mode=tsmg.TS_STENCIL_NONE)
+    try:
+        op = matfree.LevelOperator(w["x"], w["lo"], w["hi"], w["N"], w["lam"])
+        rng = np.random.default_rng(108)
+        c = rng.standard_normal(S.K())
+        assert gc.rel(S.apply(S.G, c).cpu().numpy(), op @ c) < 1e-12
+        c32 = c.astype(np.float32)
+        assert gc.rel(S.apply(S.G, c32, fp32=True).cpu().numpy(), op @ c32.astype(np.float64)) < 3e-5
+        assert gc.rel(S.rhs().cpu().numpy(), op.PhiT @ w["y"]) < 1e-12
+        assert gc.rel(S.diag(S.G).cpu().numpy(), op.diagonal()) < 1e-12
+    finally:
+        S.close()

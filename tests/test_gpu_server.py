@@ -151,3 +151,66 @@ def test_request_larger_than_budget_is_refused(reqs):
         assert e.value.status == tsmg.TS_ENOMEM
     finally:
         S.close()
+
+
+def test_one_waiter_per_ticket(reqs):
+    """Two threads waiting on one ticket: one gets the result, the other a
+    TS_EINVAL (already being waited for, or already released); the server
+    stays usable."""
+    import threading
+    r = reqs[0]
+    S = tsmg.Server(slots=1)
+    try:
+        t = S.submit(r["x"], r["y"], r["N"], r["lam"], r["lo"], r["hi"], options=_opts(tsmg.TS_FP64, 1e-10))
+        K = S._K[t]
+        out = [None, None]
+
+        def wait(i):
+            buf = np.empty(K)
+            try:
+                res = tsmg.ts_server_wait(S.handle, t, buf.ctypes.data, K)
+                out[i] = ("ok", res.status)
+            except tsmg.TsmgError as e:
+                out[i] = ("err", e.status)
+
+        th = [threading.Thread(target=wait, args=(i,)) for i in range(2)]
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        kinds = sorted(o[0] for o in out)
+        assert kinds == ["err", "ok"], out
+        assert [o[1] for o in out if o[0] == "err"] == [tsmg.TS_EINVAL]
+        assert [o[1] for o in out if o[0] == "ok"] == [tsmg.TS_OK]
+        t2 = S.submit(r["x"], r["y"], r["N"], r["lam"], r["lo"], r["hi"], options=_opts(tsmg.TS_FP64, 1e-10))
+        a, res = S.wait(t2)
+        assert res["status"] == tsmg.TS_OK and a is not None
+    finally:
+        S.close()
+
+
+def test_shortest_estimated_work_admitted_first(reqs):
+    """One slot busy with a first request; of the two queued behind it the one
+    with less estimated work per apply starts first (TS_ADMIT_SHORTEST),
+    while with TS_ADMIT_FIFO the older one does."""
+    small = min(reqs, key=lambda r: len(r["y"]) * 4 ** r["d"])
+    big = max(reqs, key=lambda r: len(r["y"]) * 4 ** r["d"])
+    assert len(big["y"]) * 4 ** big["d"] > 2 * len(small["y"]) * 4 ** small["d"]
+    for policy in (tsmg.TS_ADMIT_SHORTEST, tsmg.TS_ADMIT_FIFO):
+        S = tsmg.Server(slots=1, policy=policy, max_wait_s=1e6)
+        try:
+            o = _opts(tsmg.TS_FP64, 1e-10)
+            t0 = S.submit(big["x"], big["y"], big["N"], big["lam"], big["lo"], big["hi"], options=o)
+            import time
+            while S.stats()["active"] == 0 and not S.poll(t0):   # the first one is on the device
+                time.sleep(0.001)
+            tb = S.submit(big["x"], big["y"], big["N"], big["lam"], big["lo"], big["hi"], options=o)
+            ts = S.submit(small["x"], small["y"], small["N"], small["lam"], small["lo"], small["hi"], options=o)
+            r0, rb, rs = S.wait(t0)[1], S.wait(tb)[1], S.wait(ts)[1]
+        finally:
+            S.close()
+        assert r0["t_start"] <= min(rb["t_start"], rs["t_start"])
+        if policy == tsmg.TS_ADMIT_SHORTEST:
+            assert rs["t_start"] < rb["t_start"], (rs, rb)
+        else:
+            assert rb["t_start"] < rs["t_start"], (rs, rb)

@@ -106,6 +106,7 @@ def test_lambda_diagonal_is_diag_of_lambda():
     lo, hi = [0.0, -1.0, 0.5], [1.0, 2.0, 0.75]
     L = system.lambda_matrix(3, lo, hi, 4)
     assert np.allclose(matfree.lambda_diagonal(3, lo, hi, 4), L.diagonal(), rtol=1e-13, atol=0)
+    assert np.abs(system.lambda_dense(3, lo, hi, 4) - L.toarray()).max() <= 1e-13 * abs(L).max()
 
 
 def _table2():

@@ -102,10 +102,11 @@ typedef enum {
 } ts_coarse_solver;
 
 typedef struct {
-    int nu1, nu2;          /* pre/post Jacobi sweeps per level (Alg. 7); default 2, 2 */
+    int nu1, nu2;          /* pre/post smoothing steps per level (Alg. 7); default 1, 1 */
     double omega_scale;    /* omega_g = omega_scale / theta_g, theta_g the largest
                               Ritz value of lanczos_steps Lanczos steps on
-                              D_g^-1/2 A_g D_g^-1/2; default 1.5, must be in (0, 2)  */
+                              D_g^-1/2 A_g D_g^-1/2 (theta_g <= rho(D^-1 A_g));
+                              default 1.8, must be in (0, 2)                       */
     int lanczos_steps;     /* default 16                                             */
     double omega_fixed;    /* > 0: use this omega on every level instead             */
     ts_precision precision;/* used by ts_solve; default TS_FP64                       */
@@ -132,7 +133,10 @@ typedef struct {
     int coarse_max_iter;   /* TS_COARSE_CG: most iterations per coarse solve; 20000 */
     int coarsest_level;    /* c: the V-cycle recurses down to level c and solves A_c
                               there (Sec. 3.2.1, 3.2.4); 1 <= c <= G, default 1; the
-                              direct solver needs K_c <= 8192                        */
+                              direct solver needs K_c <= 4096                        */
+    const int32_t* degrees;/* NULL, or d B-spline degrees q_p (1..5), one per
+                              dimension, replacing ts_create's q (Sec. 2.1); read by
+                              ts_create only                                         */
 } ts_options;
 
 typedef struct {

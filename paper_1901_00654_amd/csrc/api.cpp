@@ -43,9 +43,9 @@ extern "C" {
 void ts_default_options(ts_options* o) {
   if (!o) return;
   std::memset(o, 0, sizeof(*o));
-  o->nu1 = 2;
-  o->nu2 = 2;
-  o->omega_scale = 1.5;
+  o->nu1 = 1;
+  o->nu2 = 1;
+  o->omega_scale = 1.8;
   o->lanczos_steps = 16;
   o->omega_fixed = 0.0;
   o->precision = TS_FP64;
@@ -74,8 +74,7 @@ ts_status ts_create(int d, int q, const int32_t* intervals, const double* lo, co
   TS_API_BEGIN
   need(out != nullptr, "out must not be null");
   *out = nullptr;
-  need(q == 3, "only cubic splines (q = 3) are supported");
-  Problem* P = tsmg::create_problem(d, intervals, lo, hi, n, x, y, lambda, opt);
+  Problem* P = tsmg::create_problem(d, q, intervals, lo, hi, n, x, y, lambda, opt);
   *out = new ts_problem{P};
   return TS_OK;
   TS_API_END
@@ -250,7 +249,8 @@ ts_status ts_evaluate(ts_problem* p, const double* alpha, int64_t m, const doubl
   need(m >= 0, "m must be >= 0");
   if (m == 0) return TS_OK;
   need(alpha && xq && yq, "alpha, xq and yq must not be null");
-  tsmg::hip_check(tsmg::launch_eval(P->d, alpha, xq, m, P->box, yq, P->stream), "evaluate");
+  if (P->general) tsmg::eval_general(P, alpha, m, xq, yq);
+  else tsmg::hip_check(tsmg::launch_eval(P->d, alpha, xq, m, P->box, yq, P->stream), "evaluate");
   tsmg::hip_check(hipStreamSynchronize(P->stream), "sync");
   return TS_OK;
   TS_API_END
@@ -281,15 +281,17 @@ ts_status ts_footprint(int d, int q, const int32_t* intervals, int64_t n, const 
                        size_t* bytes) {
   TS_API_BEGIN
   need(bytes != nullptr, "bytes must not be null");
-  need(q == 3, "only cubic splines (q = 3) are supported");
   need(d >= 1 && d <= tsmg::kMaxDim, "d must be in 1..5");
   need(intervals != nullptr && n >= 1, "intervals must not be null and n >= 1");
-  const int N = intervals[0];
-  for (int p = 0; p < d; ++p) need(intervals[p] == N, "all dimensions must have the same number of intervals");
-  need(N >= 2 && (N & (N - 1)) == 0, "intervals must be a power of two >= 2");
   ts_options o;
   ts_default_options(&o);
   if (opt) o = *opt;
+  for (int p = 0; p < d; ++p) need(intervals[p] >= 1, "intervals must be >= 1");
+  if (tsmg::needs_general(d, q, intervals, o.degrees)) {
+    *bytes = size_t(tsmg::footprint_general(d, q, intervals, n, o));
+    return TS_OK;
+  }
+  const int N = intervals[0];
   *bytes = size_t(tsmg::footprint_bytes(d, N, n, o, 0.0));
   return TS_OK;
   TS_API_END

@@ -432,6 +432,11 @@ template <> const float* lvl_S<float>(Level& L) { return L.S32.p; }
 // Phi'Phi c; or, on a level assembled at setup, one stencil product.
 template <typename T>
 void apply_op(Problem* P, int g, const T* c, T* out) {
+  if (P->general) {
+    apply_general<T>(P, g, c, out);
+    P->applies++;
+    return;
+  }
   Level& L = P->lev[g];
   if (L.stencil) {
     hip_check(launch_stencil_apply<T>(P->d, 0, lvl_S<T>(L), L.J, c, out, nullptr, nullptr, L.K, P->stream),
@@ -450,6 +455,10 @@ template void apply_op<float>(Problem*, int, const float*, float*);
 // out (level g) = I e (level g-1), or out -= I e when subtract is set.
 template <typename T>
 void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract) {
+  if (P->general) {
+    transfer_general<T>(P, g, true, e, out, static_cast<const T*>(nullptr), subtract);
+    return;
+  }
   const int D = P->d;
   const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
   if (P->lev[g].K <= kFusedTransferMaxK) {
@@ -482,6 +491,10 @@ template void prolong_op<float>(Problem*, int, const float*, float*, bool);
 // out (level g-1) = I' (r - sub) (level g); sub may be null.
 template <typename T>
 void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub) {
+  if (P->general) {
+    transfer_general<T>(P, g, false, r, out, sub, false);
+    return;
+  }
   const int D = P->d;
   const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
   if (P->lev[g].K <= kFusedTransferMaxK && D <= 4) {   // (d = 5 would keep its gather tables in scratch)
@@ -680,11 +693,15 @@ void profile_apply(Problem* P, int g, int reps, double* ms_lambda, double* ms_da
   hip_check(hipEventCreate(&e2), "event");
   const bool fp32 = sizeof(T) == 4;
   const DataArgs a = data_args(P, g, fp32, c, out);
+  if (P->general) {
+    profile_general<T>(P, g, c, out, reps, e0, e1, e2);
+  } else {
   hip_check(hipEventRecord(e0, P->stream), "record");
   for (int i = 0; i < reps; ++i) lambda_apply<T>(P, g, c, out);
   hip_check(hipEventRecord(e1, P->stream), "record");
   for (int i = 0; i < reps; ++i) hip_check(launch_data(P->d, fp32, kApply, a, P->stream), "data pass");
   hip_check(hipEventRecord(e2, P->stream), "record");
+  }
   hip_check(hipEventSynchronize(e2), "sync");
   float t01 = 0.f, t12 = 0.f;
   hip_check(hipEventElapsedTime(&t01, e0, e1), "elapsed");
@@ -733,6 +750,10 @@ template void dot_op<float, float>(Problem*, const float*, const float*, int64_t
 // Setup.
 
 static void compute_diag(Problem* P, int g) {
+  if (P->general) {
+    diag_general(P, g);
+    return;
+  }
   Level& L = P->lev[g];
   hip_check(launch_lambda_diag(P->d, L.band64.p, L.J, L.K, P->lam, L.diag.p, P->stream), "lambda diag");
   hip_check(launch_data(P->d, false, kDiag, data_args(P, g, false, nullptr, L.diag.p), P->stream), "data diag");
@@ -951,7 +972,7 @@ static void build_coarse(Problem* P) {
     hip_check(hipStreamSynchronize(P->stream), "sync");
     return;
   }
-  if (!L1.S64.p) {
+  if (!P->general && !L1.S64.p) {
     DevBuf<double> none;
     build_stencil(P, c, none, false);
     L1.stencil = (P->opt.stencil_mode != 1);
@@ -960,8 +981,12 @@ static void build_coarse(Problem* P) {
   P->A1.alloc(size_t(K1) * K1);
   P->A1inv.alloc(size_t(K1) * K1);
   P->cwork.alloc(size_t(2 * K1));
-  hip_check(launch_fill<double>(P->A1.p, 0.0, K1 * K1, P->stream), "fill");
-  hip_check(launch_dense_from_stencil(D, L1.S64.p, L1.J, K1, P->A1.p, P->stream), "assemble");
+  if (P->general) {
+    coarse_matrix_general(P, P->A1.p);
+  } else {
+    hip_check(launch_fill<double>(P->A1.p, 0.0, K1 * K1, P->stream), "fill");
+    hip_check(launch_dense_from_stencil(D, L1.S64.p, L1.J, K1, P->A1.p, P->stream), "assemble");
+  }
   hip_check(hipMemcpyAsync(P->A1inv.p, P->A1.p, sizeof(double) * K1 * K1, hipMemcpyDeviceToDevice, P->stream),
             "copy A1");
   // diagonal before inversion, for the pivot test
@@ -1002,7 +1027,7 @@ void check_solve_options(const ts_options& o) {
   if (o.coarse_tol < 0.0 || o.coarse_max_iter < 0) throw Error{TS_EINVAL, "coarse CG limits must be >= 0"};
 }
 
-Problem* create_problem(int d, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
+Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
                         const double* x, const double* y, double lam, const ts_options* opt,
                         double stencil_budget) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1012,17 +1037,34 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
   if (!intervals || !lo || !hi || !x || !y) throw Error{TS_EINVAL, "null argument"};
   if (n < 1) throw Error{TS_EINVAL, "n must be >= 1"};
   if (!(lam > 0.0) || !std::isfinite(lam)) throw Error{TS_EINVAL, "lambda must be finite and > 0"};
-  const int N = intervals[0];
   for (int p = 0; p < d; ++p) {
-    if (intervals[p] != N) throw Error{TS_EINVAL, "all dimensions must have the same number of intervals"};
     if (!(lo[p] < hi[p]) || !std::isfinite(lo[p]) || !std::isfinite(hi[p]))
       throw Error{TS_EINVAL, "box must satisfy lo < hi with finite bounds"};
+    if (intervals[p] < 1) throw Error{TS_EINVAL, "intervals must be >= 1"};
   }
-  if (N < 2 || (N & (N - 1)) != 0) throw Error{TS_EINVAL, "intervals must be a power of two >= 2"};
+  const int32_t* degrees = opt ? opt->degrees : nullptr;
+  int32_t qs[kMaxDim];
+  for (int p = 0; p < d; ++p) qs[p] = degrees ? degrees[p] : q;
+  const bool general = needs_general(d, q, intervals, degrees);
+  const int N = intervals[0];
   int G = 0;
-  while ((1 << G) < N) ++G;
-  if (int64_t(G) * d > 30) throw Error{TS_EINVAL, "N^d must not exceed 2^30 cells"};
-  {
+  if (general) {
+    // degree q_p and intervals N_p per dimension (Sec. 2.1)
+    double cells = 1.0, K = 1.0, patch = 1.0;
+    for (int p = 0; p < d; ++p) {
+      if (qs[p] < 1 || qs[p] > kQMax) throw Error{TS_EINVAL, "degrees must be in 1..5"};
+      cells *= intervals[p];
+      K *= intervals[p] + qs[p];
+      patch *= qs[p] + 1;
+    }
+    if (cells > double(1 << 30)) throw Error{TS_EINVAL, "prod N_p must not exceed 2^30 cells"};
+    if (K >= 2147483647.0) throw Error{TS_EINVAL, "prod (N_p + q_p) must be < 2^31"};
+    if (patch > 1024.0) throw Error{TS_EINVAL, "prod (q_p + 1) must not exceed 1024"};
+    G = general_levels(d, intervals);
+  } else {
+    if (N < 2 || (N & (N - 1)) != 0) throw Error{TS_EINVAL, "intervals must be a power of two >= 2"};
+    while ((1 << G) < N) ++G;
+    if (int64_t(G) * d > 30) throw Error{TS_EINVAL, "N^d must not exceed 2^30 cells"};
     double K = std::pow(double(N + kDeg), d);
     if (K >= 2147483647.0) throw Error{TS_EINVAL, "(N+3)^d must be < 2^31"};
   }
@@ -1033,6 +1075,7 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     P->d = d;
     P->G = G;
     P->N = N;
+    P->general = general;
     P->n = n;
     P->lam = lam;
     ts_default_options(&P->opt);
@@ -1045,7 +1088,8 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     P->Gc = P->opt.coarsest_level;
     if (P->opt.coarse_solver == TS_COARSE_DIRECT) {
       int64_t Kc = 1;
-      for (int p = 0; p < d; ++p) Kc *= (int64_t(1) << P->Gc) + kDeg;
+      for (int p = 0; p < d; ++p)
+        Kc *= general ? (intervals[p] >> (G - P->Gc)) + qs[p] : (int64_t(1) << P->Gc) + kDeg;
       if (Kc > kMaxDirectCoarse)
         throw Error{TS_EINVAL, "the direct coarse solver takes K_c <= " + std::to_string(kMaxDirectCoarse) +
                                    " coefficients (K_c = " + std::to_string(Kc) + "); use TS_COARSE_CG"};
@@ -1072,8 +1116,11 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
     P->box.G = G;
     hipStream_t st = P->stream;
 
-    // --- bin, validate, sort, place (points in Morton order of their cell)
-    {
+    // --- bin, validate, sort, place (points in Morton order of their cell;
+    // the general form: in C order)
+    if (general) {
+      setup_general_points(P, intervals, qs, lo, hi, x, y);
+    } else {
       DevBuf<uint32_t> key0, key1, idx0, idx1;
       key0.alloc(size_t(n));
       key1.alloc(size_t(n));
@@ -1120,27 +1167,41 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
 
     // --- levels g = 1..G (N_g = 2^g)
     P->lev.resize(G + 1);
-    const int64_t KG = [&] { int64_t K = 1; for (int p = 0; p < d; ++p) K *= (N + kDeg); return K; }();
+    const int64_t KG = [&] {
+      int64_t K = 1;
+      for (int p = 0; p < d; ++p) K *= general ? intervals[p] + qs[p] : N + kDeg;
+      return K;
+    }();
     for (int g = 1; g <= G; ++g) {
       Level& L = P->lev[g];
       L.g = g;
-      L.N = 1 << g;
-      L.J = L.N + kDeg;
-      L.K = 1;
-      for (int p = 0; p < d; ++p) L.K *= L.J;
-      L.tb = std::min(kTileBits[d], g);
-      if (g < P->Gc) continue;   // below the coarsest level: sizes only
-      std::vector<double> band(size_t(d) * 3 * L.J * 7);
-      for (int p = 0; p < d; ++p) {
-        std::vector<double> b1;
-        gram_band(lo[p], hi[p], L.N, b1);
-        std::copy(b1.begin(), b1.end(), band.begin() + size_t(p) * 3 * L.J * 7);
+      if (general) {
+        // sizes on every level (ts_num_coeffs), the banded factors from level c on
+        if (g < P->Gc) {
+          L.K = 1;
+          for (int p = 0; p < d; ++p) L.K *= (intervals[p] >> (G - g)) + qs[p];
+          continue;
+        }
+        setup_general_level(P, g, lo, hi);
+      } else {
+        L.N = 1 << g;
+        L.J = L.N + kDeg;
+        L.K = 1;
+        for (int p = 0; p < d; ++p) L.K *= L.J;
+        L.tb = std::min(kTileBits[d], g);
+        if (g < P->Gc) continue;   // below the coarsest level: sizes only
+        std::vector<double> band(size_t(d) * 3 * L.J * 7);
+        for (int p = 0; p < d; ++p) {
+          std::vector<double> b1;
+          gram_band(lo[p], hi[p], L.N, b1);
+          std::copy(b1.begin(), b1.end(), band.begin() + size_t(p) * 3 * L.J * 7);
+        }
+        std::vector<float> bandf(band.begin(), band.end());
+        L.band64.alloc(band.size());
+        L.band32.alloc(band.size());
+        hip_check(hipMemcpyAsync(L.band64.p, band.data(), band.size() * 8, hipMemcpyHostToDevice, st), "upload");
+        hip_check(hipMemcpyAsync(L.band32.p, bandf.data(), bandf.size() * 4, hipMemcpyHostToDevice, st), "upload");
       }
-      std::vector<float> bandf(band.begin(), band.end());
-      L.band64.alloc(band.size());
-      L.band32.alloc(band.size());
-      hip_check(hipMemcpyAsync(L.band64.p, band.data(), band.size() * 8, hipMemcpyHostToDevice, st), "upload");
-      hip_check(hipMemcpyAsync(L.band32.p, bandf.data(), bandf.size() * 4, hipMemcpyHostToDevice, st), "upload");
       L.diag.alloc(size_t(L.K));
       L.wdinv64.alloc(size_t(L.K));
       L.wdinv32.alloc(size_t(L.K));
@@ -1169,8 +1230,8 @@ Problem* create_problem(int d, const int32_t* intervals, const double* lo, const
 
     // --- assembled stencils for the levels where they pay (same A_g), and
     // the point pass's work lists on the other levels, built on a host
-    // thread meanwhile
-    {
+    // thread meanwhile (the general form runs matrix-free on every level)
+    if (!general) {
       const double budget = stencil_budget_for(stencil_budget);
       std::vector<char> want(size_t(G) + 1, 0);
       bool matrix_free = false;

@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "../../include/tsmg.h"
+#include "general.h"
 #include "launch.h"
 
 namespace tsmg {
@@ -98,6 +99,7 @@ struct Level {
   DevBuf<double> S64;              // [(7^d+1)/2][K] offset-major stencil, upper half of the offsets
   DevBuf<float> S32;
   // work list of the point pass (levels applied matrix-free)
+  GenLevel gl{};                   // general form: sizes, degrees, strides, band offsets
   DevBuf<int32_t> wl_first;        // [workgroups + 1]
   DevBuf<int4> wl_chunks;          // [chunks + 1]
   DevBuf<uint32_t> wl_items;       // [items]
@@ -117,6 +119,14 @@ struct Problem {
   bool own_stream = false;
   BoxArgs box{};
   int ppb = 256;
+
+  // general form (degree and intervals per dimension, general_setup.cpp): the
+  // points are sorted by their finest cell in C order instead, and every
+  // level is applied matrix-free by the general kernels
+  bool general = false;
+  GenBox gbox{};
+  int gq[kMaxDim] = {};
+  DevBuf<int32_t> gcell;    // [d][n] finest cell per dimension
 
   // points in Morton order of their finest cell
   DevBuf<double> t64;       // [d][n] position inside the finest cell
@@ -169,7 +179,7 @@ struct Problem {
 
 // stencil_budget > 0 caps the bytes of assembled stencils per level at that
 // value; 0 takes min(16 GB, 40% of the free device memory).
-Problem* create_problem(int d, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
+Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
                         const double* x, const double* y, double lam, const ts_options* opt,
                         double stencil_budget = 0.0);
 
@@ -186,6 +196,24 @@ template <typename T> void profile_apply(Problem* P, int g, int reps, double* ms
 template <typename TX, typename TY> void dot_op(Problem* P, const TX* x, const TY* y, int64_t K, int slot);
 
 ts_status solve(Problem* P, double* alpha, int use_start, ts_solve_info* info);
+
+// The general form (general_setup.cpp).
+bool needs_general(int d, int q, const int32_t* N, const int32_t* degrees);
+int general_levels(int d, const int32_t* N);
+// Upper estimate of the peak device bytes of a general-form problem.
+int64_t footprint_general(int d, int q, const int32_t* N, int64_t n, const ts_options& opt);
+void setup_general_points(Problem* P, const int32_t* N, const int32_t* q, const double* lo, const double* hi,
+                          const double* x, const double* y);
+void setup_general_level(Problem* P, int g, const double* lo, const double* hi);
+template <typename T> void apply_general(Problem* P, int g, const T* c, T* out);
+template <typename T>
+void transfer_general(Problem* P, int g, bool prolong, const T* in, T* out, const T* sub, bool subtract);
+template <typename T>
+void profile_general(Problem* P, int g, T* c, T* out, int reps, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2);
+void rhs_general(Problem* P, double* b);
+void diag_general(Problem* P, int g);
+void coarse_matrix_general(Problem* P, double* A);
+void eval_general(Problem* P, const double* alpha, int64_t m, const double* xq, double* yq);
 
 }  // namespace tsmg
 

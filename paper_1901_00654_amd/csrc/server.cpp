@@ -154,7 +154,7 @@ struct Server {
                   "upload y");
         ts_options o = r->opt;
         o.stream = st;
-        P.reset(create_problem(r->d, r->intervals, r->lo, r->hi, r->n, xd.p, yd.p, r->lam, &o, stencil_budget));
+        P.reset(create_problem(r->d, kDeg, r->intervals, r->lo, r->hi, r->n, xd.p, yd.p, r->lam, &o, stencil_budget));
       }   // create_problem synchronised the stream: the device copies of x, y can go
       std::vector<double>().swap(r->x);
       std::vector<double>().swap(r->y);

@@ -18,6 +18,10 @@ namespace {
 enum Slot : int { kScratch = 0, kBB = 1, kRZa = 2, kRZb = 3, kPV = 4, kRR = 5, kRR64 = 6, kRZo = 7 };
 
 void rhs_into(Problem* P, double* b) {
+  if (P->general) {
+    rhs_general(P, b);
+    return;
+  }
   const int64_t K = P->lev[P->G].K;
   hip_check(launch_fill<double>(b, 0.0, K, P->stream), "fill");
   DataArgs a{};

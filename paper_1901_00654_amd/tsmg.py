@@ -38,7 +38,7 @@ class ts_options(ctypes.Structure):
                 ("preconditioner", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("ssor_omega", ctypes.c_double), ("coarse_solver", ctypes.c_int),
                 ("coarse_tol", ctypes.c_double), ("coarse_max_iter", ctypes.c_int),
-                ("coarsest_level", ctypes.c_int)]
+                ("coarsest_level", ctypes.c_int), ("degrees", ctypes.POINTER(ctypes.c_int32))]
 
 
 class ts_solve_info(ctypes.Structure):
@@ -429,27 +429,35 @@ class Smoother:
     method synchronises it before returning.
     """
 
-    def __init__(self, x, y, N, lam, lo=None, hi=None, options=None, stream=None, **opts):
+    def __init__(self, x, y, N, lam, lo=None, hi=None, options=None, stream=None, q=3, degrees=None, **opts):
+        """N: knot intervals, one int for every dimension or one per
+        dimension; q: the B-spline degree, or degrees: one per dimension."""
         import torch
         self.torch = torch
         self.stream = stream if stream is not None else torch.cuda.Stream()
         x = torch.as_tensor(x, dtype=torch.float64)
         y = torch.as_tensor(y, dtype=torch.float64)
         n, d = x.shape
-        self.d, self.n, self.N, self.lam = int(d), int(n), int(N), float(lam)
+        self.d, self.n, self.lam = int(d), int(n), float(lam)
+        self.intervals = [int(v) for v in N] if hasattr(N, "__len__") else [int(N)] * self.d
+        self.N = self.intervals[0]
         self.lo = [0.0] * d if lo is None else [float(v) for v in lo]
         self.hi = [1.0] * d if hi is None else [float(v) for v in hi]
         opt = options if options is not None else ts_default_options()
         for k, v in opts.items():
             setattr(opt, k, v)
         opt.stream = self.stream.cuda_stream
+        self._degrees = None
+        if degrees is not None:
+            self._degrees = (ctypes.c_int32 * d)(*[int(v) for v in degrees])
+            opt.degrees = ctypes.cast(self._degrees, ctypes.POINTER(ctypes.c_int32))
         self.options = opt
         self.handle = None
         with torch.cuda.stream(self.stream):
             xd = x.to("cuda").contiguous()
             yd = y.to("cuda").contiguous()
             self.stream.synchronize()
-            self.handle = ts_create(d, 3, [N] * d, self.lo, self.hi, n, xd, yd, lam, opt)
+            self.handle = ts_create(d, int(q), self.intervals, self.lo, self.hi, n, xd, yd, lam, opt)
         self.G = ts_num_levels(self.handle)
 
     def close(self):

@@ -77,7 +77,7 @@ class MatFreeOp:
         return self._diag
 
 
-def oracle_omega(w, Ng, omega_scale=1.5, steps=16):
+def oracle_omega(w, Ng, omega_scale=1.8, steps=16):
     if assemblable(w["d"], Ng):
         A, _, _ = level_matrix(w, Ng)
     else:

@@ -37,17 +37,18 @@ def test_exports_every_declared_symbol(built):
 
 def test_defaults_and_version(built):
     o = tsmg.ts_default_options()
-    assert (o.nu1, o.nu2, o.lanczos_steps, o.precision) == (2, 2, 16, tsmg.TS_FP64)
-    assert o.omega_scale == 1.5 and o.tol == 1e-8 and o.stream is None
+    assert (o.nu1, o.nu2, o.lanczos_steps, o.precision) == (1, 1, 16, tsmg.TS_FP64)
+    assert o.omega_scale == 1.8 and o.tol == 1e-8 and o.stream is None
     assert "gfx950" in tsmg.ts_version()
 
 
 @pytest.mark.parametrize("kw,msg", [
-    (dict(q=2), "cubic"),
+    (dict(q=0), "degrees must be in 1..5"),
+    (dict(q=6), "degrees must be in 1..5"),
     (dict(lam=0.0), "lambda"),
     (dict(lam=float("nan")), "lambda"),
-    (dict(intervals=[6, 6]), "power of two"),
-    (dict(intervals=[8, 16]), "same number"),
+    (dict(intervals=[8, 0]), "intervals must be >= 1"),
+    (dict(q=5, d=5, intervals=[8] * 5, lo=[0] * 5, hi=[1] * 5), "prod (q_p + 1)"),
     (dict(d=6, intervals=[8] * 6, lo=[0] * 6, hi=[1] * 6), "d must"),
     (dict(n=0), "n must"),
     (dict(hi=[1.0, -1.0]), "box"),

@@ -34,14 +34,48 @@ def test_apply_sampled_entries(full):
 
 @pytest.mark.parametrize("precision", [tsmg.TS_FP64, tsmg.TS_MIXED_FP32, tsmg.TS_MIXED_FP32_VCYCLE])
 def test_solve_true_residual(full, precision):
+    """Whole solves at the full workload sizes to a relative FP64 residual of
+    1e-8. The oracle recomputes the residual b - A alpha: completely for c1
+    and c2; on sampled rows for c3, each row of A alpha and of b = Phi'y from
+    the points of that row's support (a relative 2-norm residual of 1e-8
+    bounds every entry by 1e-8 ||b||)."""
     w, S = full
-    if w["name"] in ("c3", "c4"):
-        pytest.skip("full-size C3/C4 solves run in the benchmark; the CPU residual check is too slow here")
+    if w["name"] == "c4":
+        pytest.skip("a whole c4 solve takes 100 s or more; bench.py times its MGCG iterations")
     S.set_options(tol=1e-8, precision=precision, max_iter=20000)
     alpha, status, info = S.solve()
-    print(w["name"], "precision", precision, info, flush=True)
+    print(w["name"], "precision", precision, {k: info[k] for k in ("iterations", "rel_residual", "solve_s")},
+          flush=True)
     assert status == tsmg.TS_OK and info["rel_residual"] <= 1e-8
     a = alpha.cpu().numpy()
-    b = matfree.rhs(w["x"], w["y"], w["lo"], w["hi"], w["N"])
-    r = b - matfree.apply(w["x"], a, w["lo"], w["hi"], w["N"], w["lam"])
-    assert np.linalg.norm(r) / np.linalg.norm(b) < 1.5e-8
+    if w["name"] in ("c1", "c2"):
+        b = matfree.rhs(w["x"], w["y"], w["lo"], w["hi"], w["N"])
+        r = b - matfree.apply(w["x"], a, w["lo"], w["hi"], w["N"], w["lam"])
+        assert np.linalg.norm(r) / np.linalg.norm(b) < 1.5e-8
+        return
+    rng = np.random.default_rng(301)
+    K = S.K()
+    ks = np.concatenate([[0, K - 1, K // 2], rng.integers(0, K, 5)])
+    Aa = matfree.apply_rows(w["x"], a, w["lo"], w["hi"], w["N"], w["lam"], ks)
+    bk = _rhs_rows(w, ks)
+    b_gpu = S.rhs().cpu().numpy()
+    assert gc.rel(b_gpu[ks], bk) < 1e-12
+    assert np.abs(bk - Aa).max() <= 1.5e-8 * np.linalg.norm(b_gpu)
+
+
+def _rhs_rows(w, ks):
+    """(Phi'y)[k] for the flat indices ks, from the points in each support."""
+    from oracle import bspline
+    x = w["x"]
+    d = x.shape[1]
+    J = w["N"] + 3
+    cells = np.stack([bspline.cell_index(x[:, p], w["lo"][p], w["hi"][p], w["N"]) for p in range(d)], axis=1)
+    out = np.zeros(len(ks))
+    for i, k in enumerate(ks):
+        jk = np.array(np.unravel_index(int(k), (J,) * d))
+        sel = np.all((cells >= jk - 3) & (cells <= jk), axis=1)
+        v = np.ones(int(sel.sum()))
+        for p in range(d):
+            v *= bspline.basis_dense(x[sel, p], w["lo"][p], w["hi"][p], w["N"], 3)[:, jk[p]]
+        out[i] = v @ w["y"][sel]
+    return out

@@ -122,7 +122,8 @@ def test_plain_and_jacobi_cg_match_oracle(lib, P):
     ref_cg, ref_mg = _table2()[P]
     w = workloads.paper_sigmoid(P, N=32)
     A, b, _, _ = system.system(w["x"], w["y"], w["lo"], w["hi"], w["N"], w["lam"])
-    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"])
+    # the settings closest to the paper's MGCG counts (R8): nu = 2, omega_g = 1.5 / theta_g
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"], nu1=2, nu2=2, omega_scale=1.5)
     try:
         its = {}
         for pc in (tsmg.TS_PC_NONE, tsmg.TS_PC_JACOBI, tsmg.TS_PC_MG):

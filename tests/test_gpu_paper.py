@@ -1,19 +1,27 @@
-"""The paper's own test problem (Sec. 4) on the GPU: MGCG iteration counts
-stay bounded under grid refinement (Fig. 2, P = 2, G = 4..7) and match the
-oracle's MGCG on the same data (Table 2's setting, P = 1, 2 at G = 5). The
-paper's own counts are not targets: its lambda, omega, nu and tolerance are
-not given (its lambda is read off Table 3, see test_oracle_paper)."""
+"""The paper's own test problem (Sec. 4) on the GPU, with the smoother the
+paper's counts point to (nu = 2, omega_g = 1.5 / theta_g) and the stopping
+tolerance its plain-CG counts fix (1e-5, see test_oracle_mg): MGCG counts
+against the oracle's and Table 2's for P = 1..3, bounded counts under grid
+refinement (Fig. 2: P = 2, G = 4..7; and P = 4, G = 4 against 5), and the
+condition number of the V-cycle-preconditioned matrix against the oracle's
+(Table 3 prints 1.82 for settings it does not give)."""
+import os
+
 import numpy as np
 import pytest
+import torch
 
 from oracle import mg
 from paper_1901_00654_amd import tsmg, workloads
 
 pytestmark = pytest.mark.gpu
 
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table2_iterations.txt")
+PAPER = dict(nu1=2, nu2=2, omega_scale=1.5)
 
-def _iters(w, tol=1e-8):
-    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"])
+
+def _iters(w, tol):
+    S = tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"], **PAPER)
     try:
         S.set_options(tol=tol, max_iter=5000)
         _, status, info = S.solve()
@@ -23,24 +31,57 @@ def _iters(w, tol=1e-8):
         S.close()
 
 
+def _table2():
+    rows = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    return {int(r[0]): (int(r[1]), int(r[2])) for r in rows}
+
+
 def test_grid_independence_2d(lib):
-    its = {G: _iters(workloads.paper_sigmoid(2, N=2 ** G)) for G in (4, 5, 6, 7)}
-    print("P=2 iterations by G", its, flush=True)
-    assert max(its.values()) <= 12 and max(its.values()) - min(its.values()) <= 3, its
+    its = {G: _iters(workloads.paper_sigmoid(2, N=2 ** G), 1e-5) for G in (4, 5, 6, 7)}
+    print("P=2 iterations by G at tol 1e-5", its, flush=True)
+    # Fig. 2: about 4 for MGCG_JAC at every G
+    assert max(its.values()) - min(its.values()) <= 2 and max(its.values()) <= 2 * 4, its
 
 
-@pytest.mark.parametrize("P", [1, 2])
-def test_iterations_match_oracle_on_paper_data(lib, P):
+@pytest.mark.parametrize("P", [1, 2, 3])
+def test_iterations_match_oracle_and_table2(lib, P):
     w = workloads.paper_sigmoid(P, N=32)
-    it_gpu = _iters(w)
-    M = mg.MG(w["x"], w["y"], w["lo"], w["hi"], w["N"], w["lam"])
+    it_gpu = _iters(w, 1e-5)
+    M = mg.MG(w["x"], w["y"], w["lo"], w["hi"], w["N"], w["lam"], **PAPER)
     lev = M.levels[M.G]
-    _, it_oracle, _ = mg.pcg(lev["A"], lev["b"], M.vcycle, tol=1e-8, maxiter=5000)
-    print("P", P, "gpu", it_gpu, "oracle", it_oracle, flush=True)
+    _, it_oracle, _ = mg.pcg(lev["A"], lev["b"], M.vcycle, tol=1e-5, maxiter=5000)
+    print("P", P, "gpu", it_gpu, "oracle", it_oracle, "Table 2", _table2()[P][1], flush=True)
     assert abs(it_gpu - it_oracle) <= 1
+    assert abs(it_gpu - _table2()[P][1]) <= 1
 
 
-def test_higher_dimensions_converge(lib):
-    its = {P: _iters(workloads.paper_sigmoid(P, N=32)) for P in (3, 4)}
-    print("G=5 iterations by P", its, flush=True)
-    assert its[3] <= 60 and its[4] <= 200, its
+def test_four_dimensions_grid_independent(lib):
+    """P = 4 (K = 1.5e6 at G = 5, beyond the oracle's assembly): the count at
+    G = 5 stays within the G = 4 count plus a third (Sec. 4: bounded counts
+    under refinement); Table 2 prints 19 at G = 5."""
+    its = {G: _iters(workloads.paper_sigmoid(4, N=2 ** G), 1e-5) for G in (4, 5)}
+    print("P=4 iterations by G at tol 1e-5", its, "Table 2 (G=5):", _table2()[4][1], flush=True)
+    assert its[5] <= 1.34 * its[4] + 2, its
+
+
+def test_kappa_BA_matches_oracle(lib):
+    """kappa(B A) at P = 2, G = 5 from the GPU's V-cycle and operator applied
+    to every unit vector, against the oracle's V-cycle matrix (Table 3's 1.82
+    belongs to the paper's unstated smoother settings; the oracle gives 3.03
+    with these)."""
+    w = workloads.paper_sigmoid(2, N=32)
+    S = tsmg.Smoother(w["x"], w["y"], 32, w["lam"], **PAPER)
+    try:
+        K = S.K()
+        E = torch.eye(K, dtype=torch.float64)
+        A = np.column_stack([S.apply(S.G, E[:, k]).cpu().numpy() for k in range(K)])
+        B = np.column_stack([S.vcycle(E[:, k]).cpu().numpy() for k in range(K)])
+    finally:
+        S.close()
+    ev = np.sort(np.real(np.linalg.eigvals(B @ A)))
+    M = mg.MG(w["x"], w["y"], w["lo"], w["hi"], 32, w["lam"], **PAPER)
+    Ao = M.levels[M.G]["A"].toarray()
+    evo = np.sort(np.real(np.linalg.eigvals(M.matrix() @ Ao)))
+    k_gpu, k_oracle = ev[-1] / ev[0], evo[-1] / evo[0]
+    print("kappa(BA) GPU %.4f oracle %.4f (Table 3: 1.82)" % (k_gpu, k_oracle), flush=True)
+    assert abs(k_gpu - k_oracle) <= 1e-6 * k_oracle

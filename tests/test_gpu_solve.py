@@ -232,10 +232,18 @@ def test_fp32_vcycle_mode_keeps_fp64_iterations(both):
     _, st, info = _solve_with(S, tol=1e-8, precision=tsmg.TS_MIXED_FP32_VCYCLE)
     assert st64 == tsmg.TS_OK and st == tsmg.TS_OK, (info64, info)
     it64 = info64["iterations"]
-    # the recipe cases with kappa(A) > 1e10 feel the FP32 rounding more
+    print("iterations FP64 %d, FP32 V-cycle %d" % (it64, info["iterations"]), flush=True)
+    assert info["rel_residual"] <= 1e-8
+    if R.name in NEAR_SINGULAR:
+        # kappa(A) >= 1e13: beyond 1 / eps_fp32^2, the FP32 V-cycle is a
+        # different preconditioner on the smallest modes; it must still reach
+        # the FP64 tolerance, within 1.5x the FP64 count (1.28x measured on c3s)
+        assert info["iterations"] <= 1.5 * it64 + 2, (info64, info)
+        return
+    # c2s (kappa(A) = 7e11) feels the FP32 rounding more than the
+    # well-conditioned cases
     slack = 0.05 if R.name in TIGHT else 0.25
     assert abs(info["iterations"] - it64) <= max(2, slack * it64), (info64, info)
-    assert info["rel_residual"] <= 1e-8
 
 
 def test_start_vector_is_used(both):

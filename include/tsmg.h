@@ -297,6 +297,33 @@ ts_status ts_footprint(int d, int q, const int32_t* intervals, int64_t n, const 
                        size_t* bytes);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as ts_create + ts_solve from a zero start + ts_destroy, with every
+ * device buffer of the problem (sorted points, level hierarchy, stencils,
+ * work lists, coarse inverse, Krylov vectors, reduction partials) carved from
+ * one static device array of TS_NOALLOC_SCRATCH_BYTES bytes per GPU, which
+ * the library holds on each GPU it runs on until the process ends. The call
+ * creates no stream, event or pinned host buffer: work runs on opt->stream,
+ * or on the null stream when that is NULL, and the call returns after that
+ * stream has finished it.
+ *   arguments  as for ts_create; alpha: device, K_G doubles, the solution
+ *   info       as for ts_solve (may be NULL); residual_history points to
+ *              thread-local host memory valid until this thread's next call
+ * Returns TS_EINVAL, before any device work, when the problem's estimated
+ * peak device memory exceeds the array (and during setup if a buffer does
+ * not fit after all), else as ts_create and ts_solve. Calls on one GPU share
+ * its array and keep the previous call's contents (every buffer is cleared
+ * where the method needs zeros); calls from several threads of a process
+ * on the same GPU are serialised by the library, and calls from separate
+ * processes do not share an array.
+ */
+#define TS_NOALLOC_SCRATCH_BYTES (64u << 20)
+ts_status ts_solve_noalloc(int d, int q, const int32_t* intervals, const double* lo, const double* hi,
+                           int64_t n, const double* x, const double* y, double lambda,
+                           const ts_options* opt, double* alpha, ts_solve_info* info);
+
+/*
  * Serving loop: independent smoothing requests (any d, grid, point count, lambda,
  * precision) submitted as they arrive and solved concurrently on one GPU.
  *

@@ -52,7 +52,42 @@ size_t pool_round(size_t b) {
 }
 }  // namespace
 
+thread_local Arena* g_arena = nullptr;
+
+namespace {
+struct ArenaRegions {
+  std::mutex m;
+  std::vector<std::pair<char*, size_t>> r;
+};
+ArenaRegions& arena_regions() {
+  static ArenaRegions* a = new ArenaRegions;
+  return *a;
+}
+bool in_arena_region(void* p) {
+  ArenaRegions& A = arena_regions();
+  std::lock_guard<std::mutex> lk(A.m);
+  for (auto& x : A.r)
+    if (static_cast<char*>(p) >= x.first && static_cast<char*>(p) < x.first + x.second) return true;
+  return false;
+}
+}  // namespace
+
+void register_arena_region(void* base, size_t bytes) {
+  ArenaRegions& A = arena_regions();
+  std::lock_guard<std::mutex> lk(A.m);
+  A.r.emplace_back(static_cast<char*>(base), bytes);
+}
+
 void* pool_alloc(size_t bytes) {
+  if (g_arena) {
+    const size_t start = (g_arena->used + 255) / 256 * 256;
+    if (start + bytes > g_arena->cap)
+      throw Error{TS_EINVAL, "problem does not fit in the " + std::to_string(g_arena->cap >> 20) +
+                                 " MiB no-allocation scratch (a block of " + std::to_string(bytes) +
+                                 " bytes after " + std::to_string(start) + " in use)"};
+    g_arena->used = start + bytes;
+    return g_arena->base + start;
+  }
   int dev = 0;
   hip_check(hipGetDevice(&dev), "get device");
   const size_t sz = pool_round(bytes);
@@ -94,6 +129,7 @@ void* pool_alloc(size_t bytes) {
 }
 
 void pool_release(void* p) {
+  if (in_arena_region(p)) return;
   Pool& P = pool();
   bool free_now = std::uncaught_exceptions() > 0;
   {
@@ -723,11 +759,12 @@ void Problem::copy_slots(int first, int count) {
   hip_check(hipMemcpyAsync(host_slots + first, slots.p + first, sizeof(double) * count, hipMemcpyDeviceToHost,
                            stream),
             "slot readback");
-  hip_check(hipEventRecord(slots_ready, stream), "record");
+  if (slots_ready) hip_check(hipEventRecord(slots_ready, stream), "record");
 }
 
 void Problem::wait_slots(int first, int count, double* host) {
-  hip_check(hipEventSynchronize(slots_ready), "event sync");
+  if (slots_ready) hip_check(hipEventSynchronize(slots_ready), "event sync");
+  else hip_check(hipStreamSynchronize(stream), "stream sync");
   std::memcpy(host, host_slots + first, sizeof(double) * count);
 }
 
@@ -900,6 +937,7 @@ static bool want_stencil(int d, int J, int64_t n, int mode, double budget) {
 
 static double stencil_budget_for(double stencil_budget) {
   if (stencil_budget > 0.0) return stencil_budget;
+  if (g_arena) return 0.5 * double(g_arena->cap - std::min(g_arena->cap, g_arena->used));
   size_t free_b = 0, total_b = 0;
   hip_check(hipMemGetInfo(&free_b, &total_b), "meminfo");
   return std::min(16e9, 0.4 * double(free_b));
@@ -1099,12 +1137,21 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
     hip_check(hipGetDevice(&P->device), "hipGetDevice");
     if (P->opt.stream) {
       P->stream = static_cast<hipStream_t>(P->opt.stream);
+    } else if (g_arena) {
+      P->stream = nullptr;   // no resources are created in the no-allocation mode
     } else {
       hip_check(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking), "stream");
       P->own_stream = true;
     }
-    hip_check(hipHostMalloc(reinterpret_cast<void**>(&P->host_slots), sizeof(double) * kSlots), "pinned");
-    hip_check(hipEventCreateWithFlags(&P->slots_ready, hipEventDisableTiming), "event");
+    if (g_arena) {
+      // host scalars in ordinary thread-local memory; readbacks synchronise the stream
+      static thread_local double host_slots[kSlots];
+      P->host_slots = host_slots;
+      P->pinned_slots = false;
+    } else {
+      hip_check(hipHostMalloc(reinterpret_cast<void**>(&P->host_slots), sizeof(double) * kSlots), "pinned");
+      hip_check(hipEventCreateWithFlags(&P->slots_ready, hipEventDisableTiming), "event");
+    }
     P->slots.alloc(kSlots);
     P->partial.alloc(kMaxPartials);
     P->flag.alloc(1);
@@ -1303,9 +1350,9 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
 }
 
 Problem::~Problem() {
-  if (stream) (void)hipStreamSynchronize(stream);
+  (void)hipStreamSynchronize(stream);   // also the null stream of the no-allocation mode
   lev.clear();
-  if (host_slots) (void)hipHostFree(host_slots);
+  if (host_slots && pinned_slots) (void)hipHostFree(host_slots);
   if (slots_ready) (void)hipEventDestroy(slots_ready);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

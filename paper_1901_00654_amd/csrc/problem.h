@@ -47,6 +47,17 @@ extern thread_local MemCount g_mem;
 void* pool_alloc(size_t bytes);
 void pool_release(void* p);
 
+// Bump allocator over a caller-provided device region. While a thread has
+// g_arena set, pool_alloc on that thread carves blocks from it (256-byte
+// aligned) and throws Error{TS_EINVAL} once it is exhausted; pool_release
+// ignores blocks inside any region registered with register_arena_region.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+extern thread_local Arena* g_arena;
+void register_arena_region(void* base, size_t bytes);
 
 // Owning device buffer, returned to the cache on destruction. Every owner
 // synchronises the stream its buffers were used on before releasing them;
@@ -159,6 +170,7 @@ struct Problem {
   DevBuf<double> partial;   // reduction partials
   DevBuf<int> flag;
   double* host_slots = nullptr;
+  bool pinned_slots = true;   // host_slots from hipHostMalloc (else caller-owned host memory)
 
   double setup_s = 0.0;
   int64_t applies = 0;

@@ -131,6 +131,8 @@ _SIGNATURES = {
     "ts_memory": (_I, [_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
     "ts_footprint": (_I, [_I, _I, ctypes.POINTER(ctypes.c_int32), _I64, ctypes.POINTER(ts_options),
                           ctypes.POINTER(ctypes.c_size_t)]),
+    "ts_solve_noalloc": (_I, [_I, _I, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_D), ctypes.POINTER(_D),
+                              _I64, _P, _P, _D, ctypes.POINTER(ts_options), _P, ctypes.POINTER(ts_solve_info)]),
     "ts_server_default_options": (None, [ctypes.POINTER(ts_server_options)]),
     "ts_server_create": (_I, [ctypes.POINTER(ts_server_options), ctypes.POINTER(_P)]),
     "ts_server_submit": (_I, [_P, ctypes.POINTER(ts_request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -308,6 +310,23 @@ def ts_footprint(d, q, intervals, n, opt=None):
     _check(load_library().ts_footprint(int(d), int(q), iv, int(n), ctypes.byref(opt) if opt is not None else None,
                                        ctypes.byref(b)))
     return b.value
+
+
+TS_NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def ts_solve_noalloc(d, q, intervals, lo, hi, n, x, y, lam, alpha, opt=None):
+    """ts_create + ts_solve + ts_destroy in the library's static device
+    scratch (no device allocation); returns (status, info)."""
+    lib = load_library()
+    iv = (ctypes.c_int32 * d)(*[int(v) for v in intervals])
+    lo_ = (ctypes.c_double * d)(*[float(v) for v in lo])
+    hi_ = (ctypes.c_double * d)(*[float(v) for v in hi])
+    info = ts_solve_info()
+    status = _check(lib.ts_solve_noalloc(int(d), int(q), iv, lo_, hi_, int(n), _ptr(x), _ptr(y), float(lam),
+                                         ctypes.byref(opt) if opt is not None else None, _ptr(alpha),
+                                         ctypes.byref(info)))
+    return status, info
 
 
 def ts_server_default_options():

@@ -155,63 +155,68 @@ def serving(tsmg, workloads, R, slots, served_precision):
     """The serving trace (first R requests): plain FP64 one request at a time,
     then a mixed-precision mode through the serving loop with Poisson arrivals
     at twice the measured FP64 capacity. Both to a relative FP64 true residual
-    of 1e-8."""
-    import numpy as np
+    of 1e-8; the served solutions are compared with the sequential FP64 ones
+    on their coefficients and on their fitted values at the data points."""
     reqs = [workloads.serving_request(i) for i in range(R)]
-
-    def opts(prec):
-        o = tsmg.ts_default_options()
-        o.precision = prec
-        o.tol = 1e-8
-        o.max_iter = 200000
-        return o
-
-    def summary(results, span):
-        lat = np.array([res["t_done"] - res["t_submit"] for _, res in results])
-        return {"solves_per_s": len(results) / span, "span_s": span,
-                "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-                "max_rel_residual": max(res["info"]["rel_residual"] for _, res in results),
-                "failed": sum(res["status"] != tsmg.TS_OK for _, res in results)}
-
-    S = tsmg.Server(slots=1)
-    seq = []
-    try:
-        for r in reqs:
-            t = S.submit(r["x"], r["y"], r["N"], r["lam"], options=opts(tsmg.TS_FP64))
-            seq.append(S.wait(t))
-    finally:
-        S.close()
-    span_seq = max(res["t_done"] for _, res in seq) - min(res["t_submit"] for _, res in seq)
+    seq, _ = serve_run(tsmg, reqs, tsmg.TS_FP64, 1, None, label="fp64 sequential")
+    s_seq = serve_summary(seq)
     out = {"requests": R, "sample": "requests 0..%d of the serving trace (d in 2..4, N in 16..64, "
                                     "n log-uniform 1e4..1e6, lambda log-uniform 1e-6..1e-2)" % (R - 1),
-           "fp64_sequential": summary(seq, span_seq)}
-    rate = 2.0 * R / span_seq
-    arrivals = workloads.poisson_arrivals(R, rate)
-    S = tsmg.Server(slots=slots)
-    try:
-        t0 = time.perf_counter()
-        tickets = []
-        for i, r in enumerate(reqs):
-            delay = t0 + arrivals[i] - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets.append(S.submit(r["x"], r["y"], r["N"], r["lam"], options=opts(served_precision)))
-        mixed = [S.wait(t) for t in tickets]
-        st = S.stats()
-    finally:
-        S.close()
-    span = max(res["t_done"] for _, res in mixed) - min(res["t_submit"] for _, res in mixed)
-    m = summary(mixed, span)
-    m.update({"precision": PRECISIONS_BY_CODE[served_precision], "slots": slots,
-              "arrival_rate_per_s": rate, "max_active": st["max_active"],
-              "max_in_use_bytes": st["max_in_use"]})
+           "fp64_sequential": s_seq}
+    rate = 2.0 * s_seq["solves_per_s"]
+    mixed, st = serve_run(tsmg, reqs, served_precision, slots, rate, label="mixed served")
+    m = serve_summary(mixed, st)
+    m.update({"precision": PRECISIONS_BY_CODE[served_precision], "slots": slots, "arrival_rate_per_s": rate})
     out["mixed_served"] = m
-    out["max_rel_diff_alpha_mixed_vs_fp64"] = max(
-        float(np.linalg.norm(a2 - a1) / np.linalg.norm(a1)) for (a1, _), (a2, _) in zip(seq, mixed)
-        if a1 is not None and a2 is not None)
+    out.update(served_differences(reqs, seq, mixed))
     out["iterations_fp64"] = [res["info"]["iterations"] for _, res in seq]
     out["iterations_mixed"] = [res["info"]["iterations"] for _, res in mixed]
     return out
+
+
+def fitted_values(alpha, x, N):
+    """s(x_i) = sum_k alpha_k phi_k(x_i) at the points of a serving request
+    (unit box, cubic B-splines on N uniform intervals per dimension, C-order
+    coefficients), with torch on the GPU: used only to compare two solutions
+    of the same request."""
+    import itertools
+    import torch
+    xt = torch.as_tensor(x, dtype=torch.float64, device="cuda")
+    a = torch.as_tensor(alpha, dtype=torch.float64, device="cuda")
+    n, d = xt.shape
+    u = xt * N
+    cell = torch.clamp(torch.floor(u), 0, N - 1)
+    t = u - cell
+    s = 1.0 - t
+    B = torch.stack([s ** 3 / 6, 2.0 / 3 - t ** 2 + t ** 3 / 2, 2.0 / 3 - s ** 2 + s ** 3 / 2, t ** 3 / 6], dim=-1)
+    cell = cell.long()
+    J = N + 3
+    out = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for combo in itertools.product(range(4), repeat=d):
+        idx = torch.zeros(n, dtype=torch.long, device="cuda")
+        wgt = torch.ones(n, dtype=torch.float64, device="cuda")
+        for p in range(d):
+            idx = idx * J + cell[:, p] + combo[p]
+            wgt = wgt * B[:, p, combo[p]]
+        out += wgt * a[idx]
+    return out
+
+
+def served_differences(reqs, base, results):
+    """Largest relative difference between two solutions of the same requests:
+    of the coefficients, and of the fitted values at the request's points."""
+    import numpy as np
+    import torch
+    dc, df = [], []
+    for r, (a1, _), (a2, _) in zip(reqs, base, results):
+        if a1 is None or a2 is None:
+            continue
+        dc.append(float(np.linalg.norm(a2 - a1) / np.linalg.norm(a1)))
+        f1 = fitted_values(a1, r["x"], r["N"])
+        f2 = fitted_values(a2, r["x"], r["N"])
+        df.append(float(torch.linalg.norm(f2 - f1) / torch.linalg.norm(f1)))
+    return {"max_rel_diff_alpha_vs_fp64_sequential": max(dc) if dc else None,
+            "max_rel_diff_fitted_vs_fp64_sequential": max(df) if df else None}
 
 
 def serve_run(tsmg, reqs, precision, slots, rate, policy=None, label=""):
@@ -274,42 +279,46 @@ def serve_summary(results, st=None):
     return out
 
 
-def serve_study(tsmg, workloads, R, slots, served_precision, R_seq=None):
+def serve_study(tsmg, workloads, R, slots, served_precision, R_seq=None, legs=None, c64=None, c_mixed=None):
     """The serving trace (first R requests): plain FP64 one request at a time
-    (capacity C64 from its first R_seq requests), then the mixed mode served
-    with `slots` concurrent solves at Poisson rates 2 C64 (throughput) and
-    0.7 x the mixed capacity measured there (latency), and plain FP64 served
-    the same way at 2 C64 (control). Each result's fitted values are compared
-    with its FP64 sequential solution."""
-    import numpy as np
+    (capacity C64 from its first R_seq requests; always run, as the
+    comparison), then the mixed mode served with `slots` concurrent solves at
+    Poisson rates 2 C64 (throughput) and 0.7 x the mixed capacity measured
+    there (latency), and plain FP64 served the same way at 2 C64 (control).
+    Each served result is compared with the FP64 sequential solution of the
+    same request (coefficients and fitted values). `legs` selects the served
+    legs ("mixed2x", "fp64_2x", "mixed07"); a capacity given as c64 /
+    c_mixed (from an earlier run) replaces the one measured here."""
     reqs = [workloads.serving_request(i) for i in range(R)]
     R_seq = R_seq or R
+    legs = legs or ["seq", "mixed2x", "fp64_2x", "mixed07"]
+    out = {"requests": R, "slots": slots,
+           "sample": "requests 0..%d of the serving trace (d in 2..4, N in 16..64, n log-uniform "
+                     "1e4..1e6, lambda log-uniform 1e-6..1e-2), each to a relative FP64 residual "
+                     "of 1e-8" % (R - 1)}
+    # the sequential FP64 solutions are the comparison for every leg
     seq, _ = serve_run(tsmg, reqs[:R_seq], tsmg.TS_FP64, 1, None, label="fp64 sequential")
     s_seq = serve_summary(seq)
-    rate = 2.0 * s_seq["solves_per_s"]
-    out = {"requests": R, "sample": "requests 0..%d of the serving trace (d in 2..4, N in 16..64, n log-uniform "
-                                    "1e4..1e6, lambda log-uniform 1e-6..1e-2), each to a relative FP64 residual "
-                                    "of 1e-8" % (R - 1),
-           "fp64_sequential": dict(s_seq, requests_timed=R_seq)}
-
-    def diffs(results):
-        # solutions of the same request by two modes: relative difference of
-        # the coefficients (their fitted values are compared in the tests)
-        d = [float(np.linalg.norm(a2 - a1) / np.linalg.norm(a1))
-             for (a1, _), (a2, _) in zip(seq, results) if a1 is not None and a2 is not None]
-        return max(d) if d else None
-
-    runs = [("mixed_served_throughput", served_precision, rate),
-            ("fp64_served_throughput", tsmg.TS_FP64, rate)]
-    for name, prec, rt in runs:
-        res, st = serve_run(tsmg, reqs, prec, slots, rt, label=name)
-        out[name] = dict(serve_summary(res, st), arrival_rate_per_s=rt, slots=slots,
-                         precision=PRECISIONS_BY_CODE[prec], max_rel_diff_alpha_vs_fp64_sequential=diffs(res))
-    rate_lat = 0.7 * out["mixed_served_throughput"]["solves_per_s"]
-    res, st = serve_run(tsmg, reqs, served_precision, slots, rate_lat, label="mixed latency")
-    out["mixed_served_latency"] = dict(serve_summary(res, st), arrival_rate_per_s=rate_lat, slots=slots,
-                                       precision=PRECISIONS_BY_CODE[served_precision],
-                                       max_rel_diff_alpha_vs_fp64_sequential=diffs(res))
+    out["fp64_sequential"] = dict(s_seq, requests_timed=R_seq)
+    if c64 is None:
+        c64 = s_seq["solves_per_s"]
+    out["fp64_capacity_per_s"] = c64
+    for leg, prec, key in (("mixed2x", served_precision, "mixed_served_throughput"),
+                           ("fp64_2x", tsmg.TS_FP64, "fp64_served_throughput")):
+        if leg in legs:
+            rate = 2.0 * c64
+            res, st = serve_run(tsmg, reqs, prec, slots, rate, label=key)
+            out[key] = dict(serve_summary(res, st), arrival_rate_per_s=rate, slots=slots,
+                            precision=PRECISIONS_BY_CODE[prec], **served_differences(reqs, seq, res))
+            if leg == "mixed2x" and c_mixed is None:
+                c_mixed = out[key]["solves_per_s"]
+    if "mixed07" in legs:
+        rate = 0.7 * c_mixed
+        res, st = serve_run(tsmg, reqs, served_precision, slots, rate, label="mixed latency")
+        out["mixed_served_latency"] = dict(serve_summary(res, st), arrival_rate_per_s=rate, slots=slots,
+                                           mixed_capacity_per_s=c_mixed,
+                                           precision=PRECISIONS_BY_CODE[served_precision],
+                                           **served_differences(reqs, seq, res))
     return out
 
 
@@ -560,6 +569,12 @@ def main():
                          "capacity, mixed served at 0.7x its capacity; prints one JSON line")
     ap.add_argument("--serve-seq", type=int, default=None,
                     help="with --serve-study: requests timed one at a time for the FP64 capacity")
+    ap.add_argument("--serve-legs", default=None,
+                    help="with --serve-study: comma-separated legs (seq, mixed2x, fp64_2x, mixed07)")
+    ap.add_argument("--serve-c64", type=float, default=None,
+                    help="with --serve-study: FP64 capacity (solves/s) measured in an earlier run")
+    ap.add_argument("--serve-cmixed", type=float, default=None,
+                    help="with --serve-study: mixed served capacity (solves/s) measured in an earlier run")
     ap.add_argument("--solve-all", action="store_true",
                     help="only whole solves of c1..c4 in every precision mode; prints one JSON line")
     ap.add_argument("--cases", default=None,
@@ -609,7 +624,9 @@ def main():
         return
     if args.serve_study:
         print(json.dumps(serve_study(tsmg, workloads, args.serve_requests, args.serve_slots,
-                                     SERVE_PRECISION[args.serve_precision](tsmg), args.serve_seq)), flush=True)
+                                     SERVE_PRECISION[args.serve_precision](tsmg), args.serve_seq,
+                                     args.serve_legs.split(",") if args.serve_legs else None,
+                                     args.serve_c64, args.serve_cmixed)), flush=True)
         return
     if args.only_serve:
         print(json.dumps(serving(tsmg, workloads, args.serve_requests, args.serve_slots,

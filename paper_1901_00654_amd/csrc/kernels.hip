@@ -890,6 +890,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_pass(TransferArgs<T> a) {
     }
   }
   a.out[k] = v;
+  if (a.a) a.a[k] = a.w[k] * v;
 }
 
 // ---------------------------------------------------------------------------
@@ -925,7 +926,7 @@ constexpr int kRestrictLanes = 32;
 
 template <int D, typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict_fused(const T* in, const T* sub, T* out, int Jc, int Jf,
-                                                           int64_t Kc) {
+                                                           int64_t Kc, const T* wj, T* aj) {
   constexpr int NT = (D == 1) ? 5 : (D == 2 ? 25 : (D == 3 ? 125 : 625));
   const int lane = threadIdx.x % kRestrictLanes;
   const int64_t k = int64_t(blockIdx.x) * (kBlock / kRestrictLanes) + threadIdx.x / kRestrictLanes;
@@ -962,7 +963,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict_fused(const T* in, const T*
   }
 #pragma unroll
   for (int m = kRestrictLanes / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-  if (lane == 0 && k < Kc) out[k] = v;
+  if (lane == 0 && k < Kc) {
+    out[k] = v;
+    if (aj) aj[k] = wj[k] * v;   // the coarse level's first Jacobi sweep from zero
+  }
 }
 
 // out (fine, Jf^D) = I_{g-1}^g e, or out -= I_{g-1}^g e when subtract is set.
@@ -1046,6 +1050,20 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* partial, 
   if (threadIdx.x == 0) *slot = v;
 }
 
+// The second stage of a reduction whose first stage wrote NV rows of nb
+// per-block partials (row j at partial + j * kMaxPartials): *slot[j] is the
+// sum of row j in index order.
+__global__ __launch_bounds__(kBlock) void k_sum_rows(const double* partial, int nb, int nv, double* slot0,
+                                                     double* slot1) {
+  __shared__ double sh[kBlock / 64];
+  for (int j = 0; j < nv; ++j) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kBlock) v += partial[j * kMaxPartials + i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) *(j == 0 ? slot0 : slot1) = v;
+  }
+}
+
 // alpha += w p; r -= w v with w = (*num) / (*den) read on the device. A step
 // with den <= 0 (a breakdown, which the host reports) leaves both unchanged.
 template <typename TA, typename T>
@@ -1058,6 +1076,43 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(TA* alpha, T* r, const T* p,
   const double w = *num / dn;
   alpha[k] = TA(double(alpha[k]) + w * double(p[k]));
   r[k] = T(double(r[k]) - w * double(v[k]));
+}
+
+// The FP64 CG step fused with the first stage of the norms the iteration
+// needs next: alpha += w p; r -= w v (w = (*num) / (*den)), and per block the
+// partial sums of r'r (row 0) and, when z is given, of r'z (row 1: the new
+// residual against the previous preconditioned one, for the flexible
+// direction update), in the same per-block split as k_dot_partial; with zf
+// given it also writes zf = wz .* r, the first Jacobi sweep of the V-cycle
+// that preconditions r next (zf may be z: each entry is read before it is
+// written). A step with den <= 0 leaves alpha and r unchanged (the host
+// reports the breakdown).
+__global__ __launch_bounds__(kBlock) void k_cg_step_norms(double* alpha, double* r, const double* p, const double* v,
+                                                          const double* z, int64_t K, const double* num,
+                                                          const double* den, double* partial, const double* wz,
+                                                          double* zf) {
+  __shared__ double sh[kBlock / 64];
+  const double dn = *den;
+  const bool ok = dn > 0.0 && isfinite(dn);
+  const double w = ok ? *num / dn : 0.0;
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < K; k += int64_t(gridDim.x) * kBlock) {
+    double rk = r[k];
+    if (ok) {
+      alpha[k] += w * p[k];
+      rk -= w * v[k];
+      r[k] = rk;
+    }
+    a0 += rk * rk;
+    if (z) a1 += rk * z[k];
+    if (zf) zf[k] = wz[k] * rk;
+  }
+  a0 = block_sum(a0, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = a0;
+  if (z) {
+    a1 = block_sum(a1, sh);
+    if (threadIdx.x == 0) partial[kMaxPartials + blockIdx.x] = a1;
+  }
 }
 
 // p = z + beta p with beta = (*num) / (*den).
@@ -1899,7 +1954,7 @@ template hipError_t launch_transfer<float>(bool, const TransferArgs<float>&, hip
 
 template <typename T, int D>
 static hipError_t launch_transfer_fused_d(bool prolong, const T* in, const T* sub, T* out, int Jc, int Jf,
-                                          int subtract, hipStream_t st) {
+                                          int subtract, const T* wj, T* aj, hipStream_t st) {
   int64_t Kc = 1, Kf = 1;
   for (int p = 0; p < D; ++p) { Kc *= Jc; Kf *= Jf; }
   if (prolong) {
@@ -1908,7 +1963,7 @@ static hipError_t launch_transfer_fused_d(bool prolong, const T* in, const T* su
   } else if constexpr (D <= 4) {
     const int per_block = kBlock / kRestrictLanes;
     hipLaunchKernelGGL((k_restrict_fused<D, T>), dim3(unsigned((Kc + per_block - 1) / per_block)), dim3(kBlock), 0,
-                       st, in, sub, out, Jc, Jf, Kc);
+                       st, in, sub, out, Jc, Jf, Kc, wj, aj);
   } else {
     return hipErrorInvalidValue;
   }
@@ -1917,22 +1972,22 @@ static hipError_t launch_transfer_fused_d(bool prolong, const T* in, const T* su
 
 template <typename T>
 hipError_t launch_transfer_fused(int D, bool prolong, const T* in, const T* sub, T* out, int Jc, int Jf,
-                                 int subtract, hipStream_t st) {
+                                 int subtract, const T* wj, T* aj, hipStream_t st) {
   switch (D) {
-    case 1: return launch_transfer_fused_d<T, 1>(prolong, in, sub, out, Jc, Jf, subtract, st);
-    case 2: return launch_transfer_fused_d<T, 2>(prolong, in, sub, out, Jc, Jf, subtract, st);
-    case 3: return launch_transfer_fused_d<T, 3>(prolong, in, sub, out, Jc, Jf, subtract, st);
-    case 4: return launch_transfer_fused_d<T, 4>(prolong, in, sub, out, Jc, Jf, subtract, st);
+    case 1: return launch_transfer_fused_d<T, 1>(prolong, in, sub, out, Jc, Jf, subtract, wj, aj, st);
+    case 2: return launch_transfer_fused_d<T, 2>(prolong, in, sub, out, Jc, Jf, subtract, wj, aj, st);
+    case 3: return launch_transfer_fused_d<T, 3>(prolong, in, sub, out, Jc, Jf, subtract, wj, aj, st);
+    case 4: return launch_transfer_fused_d<T, 4>(prolong, in, sub, out, Jc, Jf, subtract, wj, aj, st);
     case 5:
       if (!prolong) return hipErrorInvalidValue;   // restriction at d = 5 runs pass by pass
-      return launch_transfer_fused_d<T, 5>(prolong, in, sub, out, Jc, Jf, subtract, st);
+      return launch_transfer_fused_d<T, 5>(prolong, in, sub, out, Jc, Jf, subtract, wj, aj, st);
   }
   return hipErrorInvalidValue;
 }
 template hipError_t launch_transfer_fused<double>(int, bool, const double*, const double*, double*, int, int, int,
-                                                  hipStream_t);
+                                                  const double*, double*, hipStream_t);
 template hipError_t launch_transfer_fused<float>(int, bool, const float*, const float*, float*, int, int, int,
-                                                 hipStream_t);
+                                                 const float*, float*, hipStream_t);
 
 template <typename T>
 hipError_t launch_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K, hipStream_t st) {
@@ -1968,6 +2023,16 @@ hipError_t launch_dot(const TX* x, const TY* y, int64_t K, double* partial, doub
   const unsigned nb = reduce_blocks(K);
   hipLaunchKernelGGL((k_dot_partial<TX, TY>), dim3(nb), dim3(kBlock), 0, st, x, y, K, partial);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, st, partial, int(nb), slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_step_norms(double* alpha, double* r, const double* p, const double* v, const double* z,
+                                int64_t K, const double* num, const double* den, double* partial, double* rr,
+                                double* rz, const double* wz, double* zf, hipStream_t st) {
+  const unsigned nb = reduce_blocks(K);
+  hipLaunchKernelGGL(k_cg_step_norms, dim3(nb), dim3(kBlock), 0, st, alpha, r, p, v, z, K, num, den, partial, wz,
+                     zf);
+  hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, st, partial, int(nb), z ? 2 : 1, rr, rz);
   return hipGetLastError();
 }
 template hipError_t launch_dot<double, double>(const double*, const double*, int64_t, double*, double*, hipStream_t);

@@ -35,6 +35,8 @@ struct TransferArgs {
   int Jc, Jf;       // coarse / fine length of dimension p
   int subtract;     // prolongation only: out -= value instead of out = value
   const T* sub;     // restriction only: input is in - sub (null: in)
+  const T* w;       // restriction only, with a: also a = w .* out (the coarse
+  T* a;             // level's first Jacobi sweep from zero); a null: not done
 };
 
 hipError_t launch_data(int D, bool fp32, int mode, const DataArgs& a, hipStream_t st);
@@ -53,10 +55,11 @@ hipError_t launch_lambda_diag(int D, const double* band, int J, int64_t K, doubl
                               hipStream_t st);
 template <typename T> hipError_t launch_transfer(bool prolong, const TransferArgs<T>& a, hipStream_t st);
 // Whole transfer in one kernel (small levels): prolongation out (=|-=) I in,
-// or restriction out = I'(in - sub) (sub may be null).
+// or restriction out = I'(in - sub) (sub may be null), which with aj non-null
+// also writes aj = wj .* out (the coarse level's first Jacobi sweep from zero).
 template <typename T>
 hipError_t launch_transfer_fused(int D, bool prolong, const T* in, const T* sub, T* out, int Jc, int Jf,
-                                 int subtract, hipStream_t st);
+                                 int subtract, const T* wj, T* aj, hipStream_t st);
 constexpr int64_t kFusedTransferMaxK = 65536;   // fine-level size up to which the fused form is used
 
 template <typename T> hipError_t launch_jacobi_first(T* alpha, const T* wdinv, const T* b, int64_t K, hipStream_t st);
@@ -69,6 +72,11 @@ hipError_t launch_dot(const TX* x, const TY* y, int64_t K, double* partial, doub
 template <typename TA, typename T>
 hipError_t launch_cg_step(TA* alpha, T* r, const T* p, const T* v, int64_t K, const double* num,
                           const double* den, hipStream_t st);
+// FP64 CG step fused with *rr = r'r and (z non-null) *rz = r'z of the
+// updated r, and (zf non-null) zf = wz .* r; partial holds 2 * kMaxPartials.
+hipError_t launch_cg_step_norms(double* alpha, double* r, const double* p, const double* v, const double* z,
+                                int64_t K, const double* num, const double* den, double* partial, double* rr,
+                                double* rz, const double* wz, double* zf, hipStream_t st);
 template <typename T>
 hipError_t launch_p_update(T* p, const T* z, int64_t K, const double* num, const double* den, hipStream_t st);
 template <typename TI, typename TO>

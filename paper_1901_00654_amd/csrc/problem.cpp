@@ -498,7 +498,8 @@ void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract) {
   const int D = P->d;
   const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
   if (P->lev[g].K <= kFusedTransferMaxK) {
-    hip_check(launch_transfer_fused<T>(D, true, e, nullptr, out, Jc, Jf, subtract ? 1 : 0, P->stream),
+    hip_check(launch_transfer_fused<T>(D, true, e, nullptr, out, Jc, Jf, subtract ? 1 : 0, static_cast<const T*>(nullptr),
+                                       static_cast<T*>(nullptr), P->stream),
               "prolongation");
     return;
   }
@@ -524,9 +525,11 @@ void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract) {
 template void prolong_op<double>(Problem*, int, const double*, double*, bool);
 template void prolong_op<float>(Problem*, int, const float*, float*, bool);
 
-// out (level g-1) = I' (r - sub) (level g); sub may be null.
+// out (level g-1) = I' (r - sub) (level g); sub may be null. With a0 set
+// (cubic form only) also a0 = w0 .* out, the first Jacobi sweep from zero of
+// level g-1.
 template <typename T>
-void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub) {
+void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub, const T* w0, T* a0) {
   if (P->general) {
     transfer_general<T>(P, g, false, r, out, sub, false);
     return;
@@ -534,7 +537,7 @@ void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub) {
   const int D = P->d;
   const int Jc = P->lev[g - 1].J, Jf = P->lev[g].J;
   if (P->lev[g].K <= kFusedTransferMaxK && D <= 4) {   // (d = 5 would keep its gather tables in scratch)
-    hip_check(launch_transfer_fused<T>(D, false, r, sub, out, Jc, Jf, 0, P->stream), "restriction");
+    hip_check(launch_transfer_fused<T>(D, false, r, sub, out, Jc, Jf, 0, w0, a0, P->stream), "restriction");
     return;
   }
   T* X = prob_xfer<T>(P);
@@ -553,12 +556,14 @@ void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub) {
     a.Jc = Jc; a.Jf = Jf;
     a.subtract = 0;
     a.sub = (p == 0) ? sub : nullptr;
+    a.w = (p == D - 1) ? w0 : nullptr;
+    a.a = (p == D - 1) ? a0 : nullptr;
     hip_check(launch_transfer<T>(false, a, P->stream), "restriction pass");
     in = a.out;
   }
 }
-template void restrict_op<double>(Problem*, int, const double*, double*, const double*);
-template void restrict_op<float>(Problem*, int, const float*, float*, const float*);
+template void restrict_op<double>(Problem*, int, const double*, double*, const double*, const double*, double*);
+template void restrict_op<float>(Problem*, int, const float*, float*, const float*, const float*, float*);
 
 // Coarse CG slots (the outer Krylov loop uses 0..7, Lanczos 16..).
 enum CoarseSlot : int { kCbb = 8, kCrzA = 9, kCrzB = 10, kCpv = 11, kCrr = 12 };
@@ -631,9 +636,45 @@ static void ssor_step(Problem* P, int g, T* x, const T* b) {
   P->applies += 2;
 }
 
+// Where the first Jacobi sweep of the V-cycle on level g (g below the finest)
+// lands, when that sweep is the plain product alpha = w .* b that the
+// restriction producing b can write as well; null when it is not (coarsest
+// level, no pre-smoothing, SSOR, a stencil level whose first two sweeps are
+// one fused product, the general form).
+// (alpha: the output of that V-cycle.)
+template <typename T>
+T* first_sweep_target(Problem* P, int g, T* alpha) {
+  if (P->general || g <= P->Gc || P->opt.nu1 < 1) return nullptr;
+  Level& L = P->lev[g];
+  if (L.stencil) {
+    if (P->opt.smoother == TS_SMOOTH_SSOR || P->opt.nu1 != 1) return nullptr;
+    // the stencil branch below ping-pongs nu2 times after the first sweep
+    return (P->opt.nu2 % 2 == 0) ? alpha : lvl_t<T>(L);
+  }
+  return alpha;
+}
+template double* first_sweep_target<double>(Problem*, int, double*);
+template float* first_sweep_target<float>(Problem*, int, float*);
+
+template <typename T>
+static T* first_sweep_dest(Problem* P, int g) {
+  return first_sweep_target<T>(P, g, lvl_a<T>(P->lev[g]));
+}
+
+// The next coarser level's recursion: restriction of r (minus sub) to b_{g-1},
+// with the first sweep of level g-1 fused into it where possible, then the
+// V-cycle on level g-1.
+template <typename T>
+static void descend(Problem* P, int g, const T* r, const T* sub) {
+  Level& C = P->lev[g - 1];
+  T* a0 = first_sweep_dest<T>(P, g - 1);
+  restrict_op<T>(P, g, r, lvl_b<T>(C), sub, a0 ? lvl_w<T>(C) : static_cast<const T*>(nullptr), a0);
+  vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C), a0 != nullptr);
+}
+
 // One V-cycle (Alg. 7) on level g from a zero start: alpha = B_g b.
 template <typename T>
-void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
+void vcycle_op(Problem* P, int g, const T* b, T* alpha, bool pre_done) {
   if (g == P->Gc) {
     coarse_op<T>(P, b, alpha);
     return;
@@ -650,8 +691,7 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
     for (int j = 0; j < nu1; ++j) ssor_step<T>(P, g, alpha, b);
     hip_check(launch_stencil_apply<T>(P->d, 2, lvl_S<T>(L), L.J, alpha, t, b, w, K, P->stream), "residual");
     P->applies++;
-    restrict_op<T>(P, g, t, lvl_b<T>(C), static_cast<const T*>(nullptr));
-    vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
+    descend<T>(P, g, t, static_cast<const T*>(nullptr));
     prolong_op<T>(P, g, lvl_a<T>(C), alpha, true);
     for (int j = 0; j < nu2; ++j) ssor_step<T>(P, g, alpha, b);
     return;
@@ -673,14 +713,13 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
         std::swap(cur, oth);
       }
     } else if (nu1 == 1) {
-      hip_check(launch_jacobi_first<T>(cur, w, b, K, P->stream), "jacobi");
+      if (!pre_done) hip_check(launch_jacobi_first<T>(cur, w, b, K, P->stream), "jacobi");
     } else {
       hip_check(launch_fill<T>(cur, T(0), K, P->stream), "fill");
     }
     hip_check(launch_stencil_apply<T>(P->d, 2, S, L.J, cur, oth, b, w, K, P->stream), "residual");
     P->applies++;
-    restrict_op<T>(P, g, oth, lvl_b<T>(C), static_cast<const T*>(nullptr));
-    vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
+    descend<T>(P, g, oth, static_cast<const T*>(nullptr));
     prolong_op<T>(P, g, lvl_a<T>(C), cur, true);
     for (int j = 0; j < nu2; ++j) {
       hip_check(launch_stencil_apply<T>(P->d, 1, S, L.J, cur, oth, b, w, K, P->stream), "jacobi");
@@ -693,7 +732,7 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
   }
   // pre-smoothing (Alg. 6); the first sweep from zero needs no apply
   if (nu1 >= 1) {
-    hip_check(launch_jacobi_first<T>(alpha, w, b, K, P->stream), "jacobi");
+    if (!pre_done) hip_check(launch_jacobi_first<T>(alpha, w, b, K, P->stream), "jacobi");
     for (int j = 1; j < nu1; ++j) {
       apply_op<T>(P, g, alpha, t);
       hip_check(launch_jacobi<T>(alpha, w, b, t, K, P->stream), "jacobi");
@@ -703,8 +742,7 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
   }
   // r = A alpha - b, restricted (the subtraction is fused into the restriction)
   apply_op<T>(P, g, alpha, t);
-  restrict_op<T>(P, g, t, lvl_b<T>(C), b);
-  vcycle_op<T>(P, g - 1, lvl_b<T>(C), lvl_a<T>(C));
+  descend<T>(P, g, static_cast<const T*>(t), b);
   // alpha -= I e
   prolong_op<T>(P, g, lvl_a<T>(C), alpha, true);
   // post-smoothing
@@ -713,8 +751,8 @@ void vcycle_op(Problem* P, int g, const T* b, T* alpha) {
     hip_check(launch_jacobi<T>(alpha, w, b, t, K, P->stream), "jacobi");
   }
 }
-template void vcycle_op<double>(Problem*, int, const double*, double*);
-template void vcycle_op<float>(Problem*, int, const float*, float*);
+template void vcycle_op<double>(Problem*, int, const double*, double*, bool);
+template void vcycle_op<float>(Problem*, int, const float*, float*, bool);
 
 // Times `reps` launches of the Lambda passes and of the point pass of A_g.
 template <typename T>
@@ -1153,7 +1191,7 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
       hip_check(hipEventCreateWithFlags(&P->slots_ready, hipEventDisableTiming), "event");
     }
     P->slots.alloc(kSlots);
-    P->partial.alloc(kMaxPartials);
+    P->partial.alloc(2 * kMaxPartials);   // two rows of per-block partials
     P->flag.alloc(1);
     for (int p = 0; p < d; ++p) {
       P->box.lo[p] = lo[p];

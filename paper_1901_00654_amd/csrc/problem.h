@@ -167,7 +167,7 @@ struct Problem {
   DevBuf<float> r32, z32, p32, v32, d32;
 
   DevBuf<double> slots;     // device scalars
-  DevBuf<double> partial;   // reduction partials
+  DevBuf<double> partial;   // reduction partials [2][kMaxPartials]
   DevBuf<int> flag;
   double* host_slots = nullptr;
   bool pinned_slots = true;   // host_slots from hipHostMalloc (else caller-owned host memory)
@@ -201,9 +201,16 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
 
 template <typename T> void apply_op(Problem* P, int g, const T* c, T* out);
 template <typename T> void prolong_op(Problem* P, int g, const T* e, T* out, bool subtract);
-template <typename T> void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub);
+template <typename T>
+void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub, const T* w0 = nullptr, T* a0 = nullptr);
 template <typename T> void coarse_op(Problem* P, const T* b, T* x);
-template <typename T> void vcycle_op(Problem* P, int g, const T* b, T* alpha);
+// One V-cycle on level g from a zero start; pre_done: the first Jacobi sweep
+// (alpha = w .* b) was already written by the restriction that produced b.
+template <typename T> void vcycle_op(Problem* P, int g, const T* b, T* alpha, bool pre_done = false);
+// Where the first Jacobi sweep of a V-cycle on level g with output alpha
+// lands when it is the plain product w .* b (which the kernel producing b may
+// then write instead, passing pre_done); null when it is not.
+template <typename T> T* first_sweep_target(Problem* P, int g, T* alpha);
 template <typename T> void profile_apply(Problem* P, int g, int reps, double* ms_lambda, double* ms_data);
 template <typename TX, typename TY> void dot_op(Problem* P, const TX* x, const TY* y, int64_t K, int slot);
 

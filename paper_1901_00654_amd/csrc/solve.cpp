@@ -73,7 +73,7 @@ void rhs_op(Problem* P, double* b) { rhs_into(P, b); }
 // z = B r: one V-cycle in FP64, or (pc32) in FP32 on r / ||r|| with the
 // result scaled back (slot rr holds ||r||^2); with TS_PC_NONE z = r (plain
 // CG), with TS_PC_JACOBI z = D^-1 r.
-static void precondition(Problem* P, bool pc32, const double* r, double* z, int rr) {
+static void precondition(Problem* P, bool pc32, const double* r, double* z, int rr, bool pre_done = false) {
   const int G = P->G;
   const int64_t K = P->lev[G].K;
   if (P->opt.preconditioner == TS_PC_NONE) {
@@ -85,7 +85,7 @@ static void precondition(Problem* P, bool pc32, const double* r, double* z, int 
     return;
   }
   if (!pc32) {
-    vcycle_op<double>(P, G, r, z);
+    vcycle_op<double>(P, G, r, z, pre_done);
     return;
   }
   hip_check(launch_scale_copy<double, float>(r, P->r32.p, K, 1.0, P->slot(rr), P->stream), "to fp32");
@@ -139,6 +139,8 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
     info->converged = 1;
     return TS_OK;
   }
+  // where the step kernel can write the first sweep of the next V-cycle
+  double* zf = (!pc32 && P->opt.preconditioner == TS_PC_MG) ? first_sweep_target<double>(P, G, z) : nullptr;
   for (;;) {
     int sa = kRZa, sb = kRZb;
     if (pc32) dot_op<double, double>(P, r, r, K, kRR);
@@ -148,14 +150,16 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
     while (total < P->opt.max_iter) {
       apply_op<double>(P, G, p, v);
       dot_op<double, double>(P, p, v, K, kPV);
-      hip_check(launch_cg_step<double, double>(alpha, r, p, v, K, P->slot(sa), P->slot(kPV), st), "cg step");
-      dot_op<double, double>(P, r, r, K, kRR);
-      if (flex) dot_op<double, double>(P, r, z, K, kRZo);   // r_new' z_old
+      // the step with r'r, for the flexible update r_new' z_old, and the
+      // first Jacobi sweep of the V-cycle that follows
+      hip_check(launch_cg_step_norms(alpha, r, p, v, flex ? z : nullptr, K, P->slot(sa), P->slot(kPV), P->partial.p,
+                                     P->slot(kRR), P->slot(kRZo), zf ? P->lev[G].wdinv64.p : nullptr, zf, st),
+                "cg step");
       P->copy_slots(kPV, 2);
       // the next V-cycle is queued before the host reads the residual, so the
       // device does not idle during the readback; after the last iteration
       // it is wasted (z is not used again)
-      precondition(P, pc32, r, z, kRR);
+      precondition(P, pc32, r, z, kRR, zf != nullptr);
       double h[2];
       P->wait_slots(kPV, 2, h);
       ++total;

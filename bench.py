@@ -310,6 +310,7 @@ def serve_study(tsmg, workloads, R, slots, served_precision, R_seq=None, legs=No
             res, st = serve_run(tsmg, reqs, prec, slots, rate, label=key)
             out[key] = dict(serve_summary(res, st), arrival_rate_per_s=rate, slots=slots,
                             precision=PRECISIONS_BY_CODE[prec], **served_differences(reqs, seq, res))
+            print(json.dumps({"leg": key, **out[key]}), file=sys.stderr, flush=True)
             if leg == "mixed2x" and c_mixed is None:
                 c_mixed = out[key]["solves_per_s"]
     if "mixed07" in legs:
@@ -319,6 +320,7 @@ def serve_study(tsmg, workloads, R, slots, served_precision, R_seq=None, legs=No
                                            mixed_capacity_per_s=c_mixed,
                                            precision=PRECISIONS_BY_CODE[served_precision],
                                            **served_differences(reqs, seq, res))
+        print(json.dumps({"leg": "mixed_served_latency", **out["mixed_served_latency"]}), file=sys.stderr, flush=True)
     return out
 
 

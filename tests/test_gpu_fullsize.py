@@ -32,6 +32,20 @@ def test_apply_sampled_entries(full):
     assert gc.rel(out[ks], ref) < 1e-12
 
 
+def test_apply_sampled_entries_next_level(full):
+    """A_{G-1} at full size (an assembled stencil at c2..c4, matrix-free at
+    c1): the operator of the same points on N/2 intervals per dimension."""
+    w, S = full
+    rng = np.random.default_rng(302)
+    g = S.G - 1
+    K = (w["N"] // 2 + 3) ** w["d"]
+    c = rng.standard_normal(K)
+    out = S.apply(g, c).cpu().numpy()
+    ks = np.concatenate([[0, K - 1, K // 2], rng.integers(0, K, 5)])
+    ref = matfree.apply_rows(w["x"], c, w["lo"], w["hi"], w["N"] // 2, w["lam"], ks)
+    assert gc.rel(out[ks], ref) < 1e-12
+
+
 @pytest.mark.parametrize("precision", [tsmg.TS_FP64, tsmg.TS_MIXED_FP32, tsmg.TS_MIXED_FP32_VCYCLE])
 def test_solve_true_residual(full, precision):
     """Whole solves at the full workload sizes to a relative FP64 residual of

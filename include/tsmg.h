@@ -137,6 +137,13 @@ typedef struct {
     const int32_t* degrees;/* NULL, or d B-spline degrees q_p (1..5), one per
                               dimension, replacing ts_create's q (Sec. 2.1); read by
                               ts_create only                                         */
+    int deterministic;     /* 1: every result is reproducible bit for bit from run to
+                              run on the same device (fixed-order reductions in
+                              place of the point pass's LDS and global atomics, and
+                              in the setup's moment sums); the point pass costs about
+                              twice as much. Cubic splines on equal power-of-two
+                              grids only (TS_EINVAL otherwise); read by ts_create
+                              only; default 0                                        */
 } ts_options;
 
 typedef struct {

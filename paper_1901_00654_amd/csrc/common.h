@@ -46,6 +46,13 @@ struct DataArgs {
                             //  tile | kChunkFirst | kChunkLast (of its segment)}
   const uint32_t* wl_items; // [items] cell in tile | first point - chunk start << 8 | count << 20
   int wl_groups;            // workgroups of the work list
+  // Run-to-run reproducible form (needs the work list, every chunk of which
+  // is a whole segment): the point pass stores each chunk's patch (FP64,
+  // (2^tb + 3)^d entries) to det_part[chunk] and k_det_reduce adds, per
+  // coefficient, the patches of the tiles covering it in a fixed order.
+  int det;
+  double* det_part;          // [chunks][patch]
+  const int32_t* det_tile_first;   // [tiles + 1] first chunk of each tile (Morton order)
 };
 constexpr uint32_t kChunkFirst = 1u << 31;   // first chunk of a tile segment
 constexpr uint32_t kChunkLast = 1u << 30;    // last chunk of a tile segment

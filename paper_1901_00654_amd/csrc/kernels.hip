@@ -282,26 +282,36 @@ __device__ __forceinline__ void point_scatter(const PointVals<D, T>& q, T s, T (
 // positions [D][ppb], and the segment's items (work list: one packed word per
 // item; otherwise cell, first point and count tables).
 struct DataLds {
-  size_t lacc, tt, items, total;
+  size_t lacc, tt, items, slots, cells, total;
 };
 __host__ __device__ constexpr size_t lds_round(size_t b) { return (b + 15) & ~size_t(15); }
 __host__ __device__ constexpr int max_items(int ppb, int Q) { return ppb / Q + 256; }
 
-template <int D, typename T, int MODE, bool STAGE_C, bool WL>
+// With DET the per-item accumulators of one round (kBlock x V FP64) and the
+// round's item cells (one per lane group) follow.
+template <int D, typename T, int MODE, bool STAGE_C, bool WL, bool DET = false>
 __host__ __device__ constexpr DataLds data_lds(int patch, int ppb, int Q) {
   DataLds l{};
   l.lacc = (MODE == kApply && STAGE_C) ? lds_round(size_t(patch) * sizeof(T)) : 0;
   l.tt = l.lacc + lds_round(size_t(patch) * sizeof(double));
   l.items = l.tt + lds_round(size_t(D) * size_t(ppb) * sizeof(T));
-  l.total = l.items + size_t(max_items(ppb, Q)) * sizeof(int) * (WL ? 1 : 3);
+  l.slots = l.items + lds_round(size_t(max_items(ppb, Q)) * sizeof(int) * (WL ? 1 : 3));
+  l.cells = l.slots + (DET ? lds_round(size_t(kBlock) * (D == 1 ? 4 : 16) * sizeof(double)) : 0);
+  l.total = l.cells + (DET ? size_t(kBlock) * sizeof(int) : 0);
   return l;
 }
 
 // TBF >= 0: the tile side is 2^TBF (known at compile time, the usual case);
 // TBF < 0: it is a.tb (levels coarser than one full tile). WL: take the
 // segments and items from the level's precomputed work list instead of
-// deriving them from the sorted keys and cell offsets.
-template <int D, typename T, int MODE, int TBF, bool WL>
+// deriving them from the sorted keys and cell offsets. DET (with WL, whose
+// segments are single chunks): the run-to-run reproducible form - the items
+// of a segment are taken in rounds of one per lane group, each round's
+// accumulators are published in LDS and every patch entry adds them in lane
+// group order (no LDS atomics), and the segment's patch is stored to
+// det_part[chunk] for k_det_reduce instead of being added to the output with
+// atomics.
+template <int D, typename T, int MODE, int TBF, bool WL, bool DET = false>
 __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   using GP = Group<D>;
   constexpr int L = GP::L;
@@ -321,7 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   for (int p = 0; p < D; ++p) patch *= P;
   // the patch accumulator is FP64 for both precisions: LDS float atomics are
   // several times slower than FP64 ones on gfx950
-  const DataLds lay = data_lds<D, T, MODE, STAGE_C, WL>(patch, a.ppb, Q);
+  static_assert(!DET || WL, "the deterministic form runs from a work list");
+  const DataLds lay = data_lds<D, T, MODE, STAGE_C, WL, DET>(patch, a.ppb, Q);
   double* lacc = reinterpret_cast<double*>(smem_raw + lay.lacc);
   T* s_tt = reinterpret_cast<T*>(smem_raw + lay.tt);   // [D][ppb] level-g positions in the cell
   const int maxi = max_items(a.ppb, Q);
@@ -329,6 +340,8 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   int* it_cell = reinterpret_cast<int*>(s_items);
   int* it_lo = it_cell + maxi;
   int* it_cnt = it_lo + maxi;
+  double* s_slot = reinterpret_cast<double*>(smem_raw + lay.slots);   // DET: [kBlock][V]
+  int* s_jcell = reinterpret_cast<int*>(smem_raw + lay.cells);         // DET: [lane groups]
 
   int st[D];
   st[D - 1] = 1;
@@ -474,7 +487,10 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       n_items = min(n_items_all, maxi);
     }
 
-    for (int it = grp; it < n_items; it += GP::NG) {
+    // item `it` of the chunk into the lane's accumulators; returns its cell
+    // (index inside the tile), with the lane's first patch entry and the
+    // patch stride of dimension D-2
+    auto run_item = [&](int it, T (&acc)[V], int& base, int& sa) -> int {
       int j, l0, l1;
       if constexpr (WL) {
         const uint32_t w = s_items[it];
@@ -488,12 +504,12 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
       }
       int cl[D];
       morton_decode<D>(uint32_t(j), tbits, cl);
-      int base = lead_off;
+      base = lead_off;
 #pragma unroll
       for (int p = 0; p < D; ++p) base += cl[p] * st[p];
-      int sa = 0;
+      sa = 0;
       if constexpr (D >= 2) sa = st[D - 2];
-      T cv[V], acc[V];
+      T cv[V];
       if constexpr (MODE == kApply && !STAGE_C) {
         // global index of the lane's first coefficient: tile origin + local offset
         int64_t gbase = 0;
@@ -526,16 +542,83 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
         else s0 = T(1);
         point_scatter<D, T, MODE == kDiag>(q0, s0, acc);
       }
+      return j;
+    };
+
+    if constexpr (!DET) {
+      for (int it = grp; it < n_items; it += GP::NG) {
+        T acc[V];
+        int base, sa;
+        run_item(it, acc, base, sa);
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const int off = (D == 1) ? v : ((v >> 2) * sa + (v & 3));
-        atomicAdd(&lacc[base + off], double(acc[v]));
+        for (int v = 0; v < V; ++v) {
+          const int off = (D == 1) ? v : ((v >> 2) * sa + (v & 3));
+          atomicAdd(&lacc[base + off], double(acc[v]));
+        }
+      }
+    } else {
+      // rounds of one item per lane group; after each, every patch entry
+      // adds the contributions of the round's items that cover it, in lane
+      // group order
+      const int rounds = (n_items + GP::NG - 1) / GP::NG;
+      for (int rd = 0; rd < rounds; ++rd) {
+        const int it = rd * GP::NG + grp;
+        T acc[V];
+        int jc = -1;
+        if (it < n_items) {
+          int base, sa;
+          jc = run_item(it, acc, base, sa);
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[v] = T(0);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) s_slot[size_t(threadIdx.x) * V + v] = double(acc[v]);
+        if (lig == 0) s_jcell[grp] = jc;
+        __syncthreads();
+        for (int e = threadIdx.x; e < patch; e += kBlock) {
+          int el[D];
+          {
+            int rem = e;
+#pragma unroll
+            for (int p = 0; p < D; ++p) {
+              el[p] = rem / st[p];
+              rem -= el[p] * st[p];
+            }
+          }
+          double sum = 0.0;
+          for (int g2 = 0; g2 < GP::NG; ++g2) {
+            const int jg = s_jcell[g2];
+            if (jg < 0) continue;
+            int cl2[D];
+            morton_decode<D>(uint32_t(jg), tbits, cl2);
+            bool in = true;
+            int dl[D];
+#pragma unroll
+            for (int p = 0; p < D; ++p) {
+              dl[p] = el[p] - cl2[p];
+              in = in && dl[p] >= 0 && dl[p] <= kDeg;
+            }
+            if (!in) continue;
+            int lane = 0;
+#pragma unroll
+            for (int q = 0; q < NLEAD; ++q) lane = lane * 4 + dl[q];
+            const int v = (D == 1) ? dl[0] : dl[D - 2] * 4 + dl[D - 1];
+            sum += s_slot[(size_t(g2) * L + lane) * V + v];
+          }
+          lacc[e] += sum;
+        }
+        __syncthreads();
       }
     }
     if (!seg_last) continue;
     __syncthreads();
 
-    for (int e = threadIdx.x; e < patch; e += kBlock) {
+    if constexpr (DET) {
+      // the segment is this one chunk (c_cur - 1): its patch to det_part
+      double* dst = a.det_part + size_t(c_cur - 1) * size_t(patch);
+      for (int e = threadIdx.x; e < patch; e += kBlock) dst[e] = lacc[e];
+    } else for (int e = threadIdx.x; e < patch; e += kBlock) {
       const T v = T(lacc[e]);
       if (v != T(0)) {
         int rem = e;
@@ -554,6 +637,60 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   }
 }
 
+
+// The second half of the reproducible point pass: out[k] += the sum of the
+// stored patches that cover coefficient k - per dimension the one or two
+// tiles whose (2^tb + 3)-wide patch contains k, their combinations in a fixed
+// order, each tile's chunks in increasing order. One writer per entry.
+template <int D, typename T>
+__global__ __launch_bounds__(kBlock) void k_det_reduce(const double* part, const int32_t* tile_first, T* out,
+                                                       int g, int tb, int64_t K) {
+  const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (k >= K) return;
+  const int J = (1 << g) + kDeg, Tg = 1 << tb, P = Tg + kDeg, ntp = 1 << (g - tb);
+  int patch = 1;
+#pragma unroll
+  for (int p = 0; p < D; ++p) patch *= P;
+  int j[D];
+  {
+    int64_t rem = k;
+#pragma unroll
+    for (int p = D - 1; p >= 0; --p) {
+      j[p] = int(rem % J);
+      rem /= J;
+    }
+  }
+  int tc[D][2], nc[D], idx[D];
+#pragma unroll
+  for (int p = 0; p < D; ++p) {
+    nc[p] = 0;
+    idx[p] = 0;
+    const int tA = min(j[p] >> tb, ntp - 1);
+    for (int t = tA; t >= 0 && t >= tA - 1; --t) {
+      const int o = j[p] - t * Tg;
+      if (o >= 0 && o <= Tg + kDeg - 1) tc[p][nc[p]++] = t;
+    }
+  }
+  double sum = 0.0;
+  for (;;) {
+    uint32_t key = 0;
+    int e = 0;
+#pragma unroll
+    for (int p = 0; p < D; ++p) {
+      const int t = tc[p][idx[p]];
+      e = e * P + (j[p] - t * Tg);
+      for (int b = 0; b < g - tb; ++b) key |= uint32_t((t >> b) & 1) << (b * D + (D - 1 - p));
+    }
+    for (int c = tile_first[key]; c < tile_first[key + 1]; ++c) sum += part[size_t(c) * size_t(patch) + size_t(e)];
+    int p = D - 1;
+    while (p >= 0 && ++idx[p] == nc[p]) {
+      idx[p] = 0;
+      --p;
+    }
+    if (p < 0) break;
+  }
+  out[k] = T(double(out[k]) + sum);
+}
 
 // ---------------------------------------------------------------------------
 // lambda * Lambda_g c by the three-accumulator sum factorisation of
@@ -1828,26 +1965,37 @@ __global__ __launch_bounds__(kBlock) void k_stencil_color(const T* S, int J, T* 
 // Host launchers.
 static inline unsigned blocks_for(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
-template <int D, typename T, int MODE, int TBF, bool WL>
+template <int D, typename T, int MODE, int TBF, bool WL, bool DET = false>
 static hipError_t launch_data_tb(const DataArgs& a, hipStream_t st) {
   const int Tg = 1 << a.tb;
   int patch = 1;
   for (int p = 0; p < D; ++p) patch *= (Tg + kDeg);
-  const size_t lds = data_lds<D, T, MODE, Group<D>::STAGE_C, WL>(patch, a.ppb, Group<D>::Q).total;
+  const size_t lds = data_lds<D, T, MODE, Group<D>::STAGE_C, WL, DET>(patch, a.ppb, Group<D>::Q).total;
   if (a.ppb > Group<D>::PPB) return hipErrorInvalidValue;
   const unsigned grid = WL ? unsigned(a.wl_groups) : unsigned((a.n + a.ppb - 1) / a.ppb);
   if (grid == 0) return hipSuccess;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE, TBF, WL>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_data<D, T, MODE, TBF, WL, DET>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_data<D, T, MODE, TBF, WL>), dim3(grid), dim3(kBlock), lds, st, a);
+  hipLaunchKernelGGL((k_data<D, T, MODE, TBF, WL, DET>), dim3(grid), dim3(kBlock), lds, st, a);
+  if constexpr (DET) {
+    int64_t K = 1;
+    for (int p = 0; p < D; ++p) K *= (1 << a.g) + kDeg;
+    hipLaunchKernelGGL((k_det_reduce<D, T>), dim3(unsigned((K + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       a.det_part, a.det_tile_first, static_cast<T*>(a.out), a.g, a.tb, K);
+  }
   return hipGetLastError();
 }
 
 template <int D, typename T, int MODE>
 static hipError_t launch_data_d(const DataArgs& a, hipStream_t st) {
+  if (a.det) {
+    if (!a.wl_items || !a.det_part || !a.det_tile_first) return hipErrorInvalidValue;
+    if (a.tb == kTileBits[D]) return launch_data_tb<D, T, MODE, kTileBits[D], true, true>(a, st);
+    return launch_data_tb<D, T, MODE, -1, true, true>(a, st);
+  }
   if constexpr (MODE == kApply) {
     if (a.wl_items) {
       if (a.tb == kTileBits[D]) return launch_data_tb<D, T, MODE, kTileBits[D], true>(a, st);
@@ -2215,7 +2363,7 @@ template hipError_t launch_gemv<double, double, float>(const double*, int, const
                                                        float*, hipStream_t);
 
 hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n,
-                                int G, int g, double* mom, hipStream_t st) {
+                                int G, int g, double* mom, bool det, hipStream_t st) {
   int nrest = 1;
   for (int p = 1; p < D; ++p) nrest *= 7;
   const int nr = nrest < kBlock ? nrest : kBlock;
@@ -2226,6 +2374,7 @@ hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, 
   int64_t chunks = (4096 + int64_t(gx) * gy - 1) / (int64_t(gx) * gy);
   const int64_t per_cell = n / int64_t(ncells) + 1;
   chunks = std::max<int64_t>(1, std::min<int64_t>({chunks, 1024, (per_cell + 255) / 256}));
+  if (det) chunks = 1;   // one block per cell: no atomics, a fixed summation order
   const dim3 grid(gx, gy, unsigned(chunks));
   switch (D) {
     case 1: hipLaunchKernelGGL(k_level_moments<1>, grid, dim3(kBlock), 0, st, t64, cell, off, n, G, g, mom); break;

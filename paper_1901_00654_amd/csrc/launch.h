@@ -118,7 +118,7 @@ hipError_t launch_gemv(const double* A, int K, const TB* base, double s, const T
 
 // Assembled 7^D stencil of a level (moments -> D Kronecker passes -> finalize).
 hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n,
-                                int G, int g, double* mom, hipStream_t st);
+                                int G, int g, double* mom, bool det, hipStream_t st);
 // One dimension of the level g -> g-1 moment change of variables (Nc = N_{g-1}).
 hipError_t launch_moments_coarsen(const double* in, double* out, int Nc, int64_t outer, int64_t inner,
                                   hipStream_t st);

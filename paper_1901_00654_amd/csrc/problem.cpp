@@ -337,7 +337,7 @@ static void lambda_apply(Problem* P, int g, const T* c, T* out) {
   }
 }
 
-static DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out) {
+DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out) {
   Level& L = P->lev[g];
   DataArgs a{};
   a.tfrac = fp32 ? static_cast<const void*>(P->t32.p) : static_cast<const void*>(P->t64.p);
@@ -358,6 +358,11 @@ static DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out
     a.wl_items = L.wl_items.p;
     a.wl_groups = L.wl_groups;
   }
+  if (P->det) {
+    a.det = 1;
+    a.det_part = P->det_part.p;
+    a.det_tile_first = L.det_tile_first.p;
+  }
   return a;
 }
 
@@ -376,6 +381,7 @@ struct WorkListHost {
   std::vector<int32_t> first;   // per workgroup: its first chunk (one past the last entry: the end)
   std::vector<int4> chunks;
   std::vector<uint32_t> items;
+  std::vector<int32_t> tile_first;   // per tile in Morton order: its first chunk; then the number of chunks
 };
 
 // Host side only (no device calls), so that it can run on a host thread.
@@ -392,7 +398,9 @@ static WorkListHost make_worklist(int D, int G, int g, int tb, int64_t ppb, cons
   std::vector<int4>& chunks = w.chunks;
   std::vector<uint32_t>& items = w.items;
   int64_t wg_points = 0;
+  w.tile_first.resize(size_t(ntiles) + 1);
   for (int64_t t = 0; t < ntiles; ++t) {
+    w.tile_first[size_t(t)] = int32_t(chunks.size());   // the chunks of a tile are contiguous
     const int64_t c0 = t << (D * tb);
     const int64_t a = cell_start(c0), b = cell_start(c0 + cells_in_tile);
     if (a == b) continue;
@@ -435,6 +443,7 @@ static WorkListHost make_worklist(int D, int G, int g, int tb, int64_t ppb, cons
     if (int64_t(items.size()) >= INT32_MAX || int64_t(chunks.size()) >= INT32_MAX)
       throw Error{TS_EINVAL, "work list exceeds 2^31 entries"};
   }
+  w.tile_first[size_t(ntiles)] = int32_t(chunks.size());
   first.push_back(int32_t(chunks.size()));
   chunks.push_back(make_int4(0, 0, int(items.size()), 0));
   if (items.empty()) items.push_back(0u);
@@ -448,6 +457,16 @@ static void upload_worklist(Problem* P, int g, const WorkListHost& w) {
   const std::vector<uint32_t>& items = w.items;
   hipStream_t st = P->stream;
   L.wl_groups = int(first.size()) - 1;
+  if (P->det) {
+    // every chunk must be a whole segment: its patch is stored, not added
+    for (size_t c = 0; c + 1 < chunks.size(); ++c)
+      if ((uint32_t(chunks[c].w) & (kChunkFirst | kChunkLast)) != (kChunkFirst | kChunkLast))
+        throw Error{TS_EINVAL, "work list chunk is not a whole segment"};
+    L.det_tile_first.alloc(w.tile_first.size());
+    hip_check(hipMemcpyAsync(L.det_tile_first.p, w.tile_first.data(), w.tile_first.size() * sizeof(int32_t),
+                             hipMemcpyHostToDevice, st),
+              "upload");
+  }
   L.wl_first.alloc(first.size());
   L.wl_chunks.alloc(chunks.size());
   L.wl_items.alloc(items.size());
@@ -912,7 +931,8 @@ static void build_stencil(Problem* P, int g, DevBuf<double>& mom, bool want_coar
   if (!src) {
     bufA.alloc(size_t(max_sz));
     hip_check(launch_fill<double>(bufA.p, 0.0, in_sz, P->stream), "fill");
-    hip_check(launch_level_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, g, bufA.p, P->stream), "moments");
+    hip_check(launch_level_moments(D, P->t64.p, P->cell.p, P->off.p, P->n, P->G, g, bufA.p, P->det, P->stream),
+              "moments");
     src = bufA.p;
   }
   bufB.alloc(size_t(max_sz));
@@ -992,20 +1012,25 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
   // binning and sort temporaries (keys and indices double-buffered, radix
   // sort scratch bounded by another key/value pair and 1 MB)
   const int64_t sort_tmp = 24 * n + (1 << 20);
-  int64_t levels = 0, stencils = 0, stencil_tmp = 0;
+  int64_t levels = 0, stencils = 0, stencil_tmp = 0, det_part = 0;
   const int Gc = std::max(1, std::min(G, opt.coarsest_level));
   const bool direct = opt.coarse_solver != TS_COARSE_CG;
+  const bool det = opt.deterministic == 1;
   for (int g = Gc; g <= G; ++g) {
     const int J = (1 << g) + kDeg;
     const int64_t K = ipow(J, d);
     levels += 56 * K + int64_t(d) * 3 * J * 7 * 12;
     const bool st = want_stencil(d, J, n, opt.stencil_mode, stencil_budget_for(stencil_budget));
-    if (!st) {   // work list: items <= n; workgroups <= chunks <= nonempty tiles
-                 // + n / 64 (ppb >= 64)
+    if (!st || det) {   // work list: items <= n; workgroups <= chunks <= nonempty tiles
+                        // + n / 64 (ppb >= 64)
       const int tb = std::min(kTileBits[d], g);
       const int64_t ntiles = int64_t(1) << (d * (g - tb));
       const int64_t chunks = std::min(n, ntiles) + n / 64 + 2;
       levels += 20 * chunks + 4 * n + 4;
+      if (det) {   // the tile index and the stored patches of the largest level
+        levels += 4 * (ntiles + 1);
+        det_part = std::max(det_part, chunks * ipow((int64_t(1) << tb) + kDeg, d) * 8);
+      }
     }
     // with the direct coarse solver level c carries its stencil: A_c is expanded from it
     if ((g == Gc && direct) || st) {
@@ -1019,7 +1044,7 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
   const int64_t coarse = direct ? 2 * K1 * K1 * 8 + 2 * K1 * 8 : 6 * K1 * 8 + K1 * 4;
   const int64_t finest = KG * (6 * 12 + 2 * 12 + 5 * 8 + 5 * 4);
   const int64_t misc = 16 * 8 + kMaxPartials * 8 + 64;
-  const int64_t steady = points + levels + stencils + coarse + finest + misc;
+  const int64_t steady = points + levels + stencils + coarse + finest + misc + det_part;
   // allocation granularity: round every buffer up, roughly 40 buffers per level
   const int64_t slack = int64_t(64) * 4096 * (G + 2);
   return steady + std::max(sort_tmp, stencil_tmp) + slack;
@@ -1162,6 +1187,10 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
     if (P->opt.coarsest_level < 1 || P->opt.coarsest_level > G)
       throw Error{TS_EINVAL, "coarsest_level must be in 1..G = " + std::to_string(G)};
     P->Gc = P->opt.coarsest_level;
+    if (P->opt.deterministic != 0 && P->opt.deterministic != 1) throw Error{TS_EINVAL, "deterministic must be 0 or 1"};
+    P->det = P->opt.deterministic == 1;
+    if (P->det && general)
+      throw Error{TS_EINVAL, "the deterministic mode takes cubic splines on equal power-of-two grids"};
     if (P->opt.coarse_solver == TS_COARSE_DIRECT) {
       int64_t Kc = 1;
       for (int p = 0; p < d; ++p)
@@ -1321,9 +1350,14 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
       std::vector<char> want(size_t(G) + 1, 0);
       bool matrix_free = false;
       const int Gc = P->Gc;
+      // work lists on the levels applied matrix-free; in the deterministic
+      // mode on every level (the setup's diagonal and right-hand-side passes
+      // take them too)
+      std::vector<char> listed(size_t(G) + 1, 0);
       for (int g = Gc; g <= G; ++g) {
         want[size_t(g)] = want_stencil(d, P->lev[g].J, n, P->opt.stencil_mode, budget);
-        matrix_free = matrix_free || !want[size_t(g)];
+        listed[size_t(g)] = !want[size_t(g)] || P->det;
+        matrix_free = matrix_free || listed[size_t(g)];
       }
       std::vector<int32_t> off_h;
       if (matrix_free) {
@@ -1335,10 +1369,10 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
       std::vector<int> tbs(size_t(G) + 1);
       for (int g = 1; g <= G; ++g) tbs[size_t(g)] = P->lev[g].tb;
       const int64_t ppb = P->ppb;
-      auto lists = std::async(std::launch::async, [&want, &off_h, tbs, ppb, d, G, Gc]() {
+      auto lists = std::async(std::launch::async, [&listed, &off_h, tbs, ppb, d, G, Gc]() {
         std::vector<WorkListHost> r(size_t(G) + 1);
         for (int g = Gc; g <= G; ++g)
-          if (!want[size_t(g)]) r[size_t(g)] = make_worklist(d, G, g, tbs[size_t(g)], ppb, off_h);
+          if (listed[size_t(g)]) r[size_t(g)] = make_worklist(d, G, g, tbs[size_t(g)], ppb, off_h);
         return r;
       });
       // finest first: each level's moments give the next coarser level's
@@ -1349,7 +1383,17 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
       }
       const std::vector<WorkListHost> wl = lists.get();
       for (int g = Gc; g <= G; ++g)
-        if (!want[size_t(g)]) upload_worklist(P, g, wl[size_t(g)]);
+        if (listed[size_t(g)]) upload_worklist(P, g, wl[size_t(g)]);
+      if (P->det) {
+        // the stored patches of the largest level (applies run one at a time)
+        size_t part = 1;
+        for (int g = Gc; g <= G; ++g) {
+          size_t patch = 1;
+          for (int p = 0; p < d; ++p) patch *= size_t((1 << P->lev[g].tb) + kDeg);
+          part = std::max(part, (wl[size_t(g)].chunks.size() - 1) * patch);
+        }
+        P->det_part.alloc(part);
+      }
     }
 
     // --- Jacobi diagonals and damping (Alg. 5, Alg. 6)

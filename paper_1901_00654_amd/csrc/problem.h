@@ -115,6 +115,7 @@ struct Level {
   DevBuf<int4> wl_chunks;          // [chunks + 1]
   DevBuf<uint32_t> wl_items;       // [items]
   int wl_groups = 0;
+  DevBuf<int32_t> det_tile_first;  // deterministic mode: [tiles + 1] first chunk of each tile
 };
 
 constexpr int kSlots = 80;
@@ -168,6 +169,8 @@ struct Problem {
 
   DevBuf<double> slots;     // device scalars
   DevBuf<double> partial;   // reduction partials [2][kMaxPartials]
+  bool det = false;         // opt.deterministic: reproducible point passes and moments
+  DevBuf<double> det_part;  // deterministic point pass: [chunks][patch] of the largest level
   DevBuf<int> flag;
   double* host_slots = nullptr;
   bool pinned_slots = true;   // host_slots from hipHostMalloc (else caller-owned host memory)
@@ -204,6 +207,9 @@ template <typename T> void prolong_op(Problem* P, int g, const T* e, T* out, boo
 template <typename T>
 void restrict_op(Problem* P, int g, const T* r, T* out, const T* sub, const T* w0 = nullptr, T* a0 = nullptr);
 template <typename T> void coarse_op(Problem* P, const T* b, T* x);
+// Arguments of the point pass on level g (its work list and, in the
+// deterministic mode, the stored-patch area) for input c and output out.
+DataArgs data_args(Problem* P, int g, bool fp32, const void* c, void* out);
 // One V-cycle on level g from a zero start; pre_done: the first Jacobi sweep
 // (alpha = w .* b) was already written by the restriction that produced b.
 template <typename T> void vcycle_op(Problem* P, int g, const T* b, T* alpha, bool pre_done = false);

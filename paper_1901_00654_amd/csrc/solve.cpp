@@ -24,20 +24,7 @@ void rhs_into(Problem* P, double* b) {
   }
   const int64_t K = P->lev[P->G].K;
   hip_check(launch_fill<double>(b, 0.0, K, P->stream), "fill");
-  DataArgs a{};
-  a.tfrac = P->t64.p;
-  a.cell = P->cell.p;
-  a.mkey = P->mkey.p;
-  a.y = P->ys.p;
-  a.off = P->off.p;
-  a.c = nullptr;
-  a.out = b;
-  a.n = P->n;
-  a.G = P->G;
-  a.g = P->G;
-  a.tb = P->lev[P->G].tb;
-  a.ppb = P->ppb;
-  hip_check(launch_data(P->d, false, kRhs, a, P->stream), "rhs");
+  hip_check(launch_data(P->d, false, kRhs, data_args(P, P->G, false, nullptr, b), P->stream), "rhs");
 }
 
 // r = b - A alpha (FP64); uses v as work space.

@@ -38,7 +38,8 @@ class ts_options(ctypes.Structure):
                 ("preconditioner", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("ssor_omega", ctypes.c_double), ("coarse_solver", ctypes.c_int),
                 ("coarse_tol", ctypes.c_double), ("coarse_max_iter", ctypes.c_int),
-                ("coarsest_level", ctypes.c_int), ("degrees", ctypes.POINTER(ctypes.c_int32))]
+                ("coarsest_level", ctypes.c_int), ("degrees", ctypes.POINTER(ctypes.c_int32)),
+                ("deterministic", ctypes.c_int)]
 
 
 class ts_solve_info(ctypes.Structure):

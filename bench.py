@@ -667,7 +667,11 @@ def main():
                 "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": tr,
                 "kernel": "k_data<3,double,apply> (point pass, finest level)",
                 "ms_per_launch": ms_data, "algorithmic_flop": flops, "algorithmic_bytes": nbytes,
-                "algorithmic_GBps": nbytes / t_data / 1e9}
+                "algorithmic_GBps": nbytes / t_data / 1e9,
+                # the same launch against the other roof: algorithmic and
+                # counted HBM bytes over the 8 TB/s peak
+                "hbm_frac_algorithmic": nbytes / t_data / 1e9 / PEAK_HBM_GBPS,
+                "hbm_frac_measured": (tr / t_data / 1e9 / PEAK_HBM_GBPS) if tr else None}
 
     result = {
         "metric": METRIC, "value": 1.0 / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,

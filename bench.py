@@ -582,6 +582,8 @@ def main():
     ap.add_argument("--cases", default=None,
                     help="with --solve-all: comma-separated workloads, e.g. c3 or c4/16")
     ap.add_argument("--modes", default=None, help="with --solve-all: comma-separated modes (fp64,mixed,vcycle32)")
+    ap.add_argument("--ref-tol", type=float, default=1e-12,
+                    help="with --solve-all: tolerance of the FP64 reference solve (default 1e-12)")
     ap.add_argument("--no-reference", action="store_true",
                     help="with --solve-all: skip the tight FP64 reference solve and the distances to it")
     ap.add_argument("--paper", action="store_true",
@@ -619,7 +621,7 @@ def main():
     if args.solve_all:
         print(json.dumps(solve_all(tsmg, torch, workloads, stream, args.cases.split(",") if args.cases else None,
                                    args.modes.split(",") if args.modes else None,
-                                   None if args.no_reference else 1e-12)), flush=True)
+                                   None if args.no_reference else args.ref_tol)), flush=True)
         return
     if args.paper:
         print(json.dumps(paper_experiments(tsmg, torch, workloads)), flush=True)

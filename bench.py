@@ -39,13 +39,14 @@ PRECISIONS_BY_CODE = {0: "fp64", 1: "mixed (FP32 CG, reliable FP64 updates)",
                       3: "vcycle32 (FP64 CG, FP32 V-cycle)"}
 
 
-def algorithmic(d, n, K, fp32):
+def algorithmic(d, n, K, fp32, q=3):
     """FLOP and bytes one point pass must spend: per point the d*4 cubic values
     (15 d FLOP), the tensor product (4^d), gather (2 * 4^d) and scatter
-    (2 * 4^d); per point its d cell coordinates and cell index; per
-    coefficient one read of c and one write of the output."""
+    (2 * 4^d) - with (q+1)^d in place of 4^d for degree q; per point its d
+    cell coordinates and cell index; per coefficient one read of c and one
+    write of the output."""
     s = 4 if fp32 else 8
-    flops = n * (5 * 4 ** d + 15 * d)
+    flops = n * (5 * (q + 1) ** d + 15 * d)
     nbytes = n * (d * s + 4) + 2 * K * s
     return flops, nbytes
 
@@ -90,7 +91,8 @@ def make_problem(tsmg, w, xd, yd, stream, precision, tol=1e-8):
     opt.max_iter = 100000
     set_smoother(opt)
     d = w["d"]
-    return tsmg.ts_create(d, 3, [w["N"]] * d, w["lo"], w["hi"], len(w["y"]), xd, yd, w["lam"], opt)
+    return tsmg.ts_create(d, SMOOTHER.get("degree", 3), [w["N"]] * d, w["lo"], w["hi"], len(w["y"]), xd, yd,
+                          w["lam"], opt)
 
 
 def run_steps(tsmg, torch, w, xd, yd, stream, precision, steps, warmup):
@@ -129,14 +131,15 @@ def apply_rate(tsmg, torch, w, stream, reps):
     yd = torch.from_numpy(w["y"]).cuda()
     torch.cuda.synchronize()
     h = make_problem(tsmg, w, xd, yd, stream, tsmg.TS_FP64)
-    out = {"workload": w["name"], "d": w["d"], "N": w["N"], "n": len(w["y"])}
+    q = SMOOTHER.get("degree", 3)
+    out = {"workload": w["name"], "d": w["d"], "N": w["N"], "n": len(w["y"]), "degree": q}
     try:
         G = tsmg.ts_num_levels(h)
         K = tsmg.ts_num_coeffs(h, G)
         for fp32 in (False, True):
             tsmg.ts_profile_apply(h, G, fp32, 2)
             ms_l, ms_d = tsmg.ts_profile_apply(h, G, fp32, reps)
-            fl, by = algorithmic(w["d"], len(w["y"]), K, fp32)
+            fl, by = algorithmic(w["d"], len(w["y"]), K, fp32, q)
             s = 4 if fp32 else 8
             by_total = by + 2 * K * s * w["d"]      # Lambda passes stream the tensors too
             t = (ms_l + ms_d) * 1e-3
@@ -596,6 +599,11 @@ def main():
     ap.add_argument("--ppb", type=int, default=None, help="points per workgroup of the point pass (default: auto)")
     ap.add_argument("--no-c3", action="store_true", help="skip the whole c3 solves")
     ap.add_argument("--no-c4", action="store_true", help="skip the c4 per-iteration timing")
+    ap.add_argument("--intervals", type=int, default=None,
+                    help="with --only-apply: knot intervals per dimension instead of the workload's (any N >= 1; "
+                         "other than a power of two it runs the general form)")
+    ap.add_argument("--degree", type=int, default=None,
+                    help="with --only-apply: B-spline degree 1..5 (other than 3 it runs the general form)")
     ap.add_argument("--only-apply", default=None, metavar="WORKLOAD",
                     help="only time the finest-level operator apply of one workload (c1..c4), "
                          "for profiling runs; prints one JSON line")
@@ -636,8 +644,10 @@ def main():
         print(json.dumps(serving(tsmg, workloads, args.serve_requests, args.serve_slots,
                                  SERVE_PRECISION[args.serve_precision](tsmg))), flush=True)
         return
+    if args.degree is not None:
+        SMOOTHER["degree"] = args.degree
     if args.only_apply:
-        wk = workloads.CONFIGS[args.only_apply]()
+        wk = workloads.CONFIGS[args.only_apply](**({"N": args.intervals} if args.intervals else {}))
         res = apply_rate(tsmg, torch, wk, stream, args.reps)
         if args.copy_calibration:
             res["copy_calibration_bytes"] = copy_calibration(torch)

@@ -64,58 +64,101 @@ __device__ __forceinline__ int level_basis(const GenPoints& pts, const GenLevel&
 }
 
 // out += Phi_g'(Phi_g c) (kApply), Phi_g'y (kRhs) or diag(Phi_g'Phi_g)
-// (kDiag), one thread per point, the scatter by atomics.
+// (kDiag), one thread per point. The patch entries are walked as an
+// odometer over the d digits (no divisions per entry). Points are sorted by
+// their finest cell, so neighbouring lanes of a wave often share a level-g
+// cell and hence every patch entry: before each entry's atomic, the lanes of
+// such a run add their contributions by a segmented shuffle reduction and
+// only the run's first lane adds the sum to the output.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kBlock) void k_data_gen(GenPoints pts, GenLevel L, const T* c, T* out) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= pts.n) return;
+  const bool live = i < pts.n;   // every lane takes part in the shuffles
   const int d = L.d;
   T b[kMaxDim][kQMax + 1];
-  int64_t base = 0;
+  int64_t base = -1 - int64_t(threadIdx.x & 63);   // distinct for lanes past the end
   int P = 1;
+  if (live) {
+    base = 0;
 #pragma unroll
-  for (int p = 0; p < kMaxDim; ++p) {
-    if (p < d) {
-      const int cg = level_basis<T>(pts, L, p, i, b[p]);
-      base += int64_t(cg) * L.stride[p];
-      P *= L.q[p] + 1;
+    for (int p = 0; p < kMaxDim; ++p) {
+      if (p < d) {
+        const int cg = level_basis<T>(pts, L, p, i, b[p]);
+        base += int64_t(cg) * L.stride[p];
+        P *= L.q[p] + 1;
+      }
     }
+  } else {
+#pragma unroll
+    for (int p = 0; p < kMaxDim; ++p)
+#pragma unroll
+      for (int m = 0; m <= kQMax; ++m) b[p][m] = T(0);
   }
-  T s = T(0);
-  if constexpr (MODE == kApply) {
+  // entry e as digits a[p]: index idx = base + sum_p a[p] stride[p]
+  auto walk = [&](auto&& body) {
+    int a[kMaxDim];
+#pragma unroll
+    for (int p = 0; p < kMaxDim; ++p) a[p] = 0;
+    int64_t idx = base;
     for (int e = 0; e < P; ++e) {
-      int rem = e;
-      int64_t idx = base;
       T w = T(1);
 #pragma unroll
-      for (int p = kMaxDim - 1; p >= 0; --p) {
-        if (p < d) {
-          const int a = rem % (L.q[p] + 1);
-          rem /= L.q[p] + 1;
-          w *= pick<T>(b[p], a);
-          idx += int64_t(a) * L.stride[p];
-        }
-      }
-      s += w * c[idx];
-    }
-  } else if constexpr (MODE == kRhs) {
-    s = T(pts.y[i]);
-  }
-  for (int e = 0; e < P; ++e) {
-    int rem = e;
-    int64_t idx = base;
-    T w = T(1);
+      for (int p = 0; p < kMaxDim; ++p)
+        if (p < d) w *= pick<T>(b[p], a[p]);
+      body(idx, w);
 #pragma unroll
-    for (int p = kMaxDim - 1; p >= 0; --p) {
-      if (p < d) {
-        const int a = rem % (L.q[p] + 1);
-        rem /= L.q[p] + 1;
-        w *= pick<T>(b[p], a);
-        idx += int64_t(a) * L.stride[p];
+      for (int p = kMaxDim - 1; p >= 0; --p) {
+        if (p >= d) continue;
+        if (a[p] < L.q[p]) {
+          ++a[p];
+          idx += L.stride[p];
+          break;
+        }
+        idx -= int64_t(a[p]) * L.stride[p];
+        a[p] = 0;
       }
     }
-    atomicAdd(&out[idx], MODE == kDiag ? w * w : s * w);
+  };
+  T s = T(0);
+  if constexpr (MODE == kApply) {
+    if (live) walk([&](int64_t idx, T w) { s += w * c[idx]; });
+  } else if constexpr (MODE == kRhs) {
+    if (live) s = T(pts.y[i]);
   }
+  // runs of lanes with the same level-g cell (the same patch)
+  const int lane = threadIdx.x & 63;
+  const int64_t prev = __shfl_up(base, 1);
+  const bool head = lane == 0 || prev != base;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+  const int seg_end = above ? __ffsll(static_cast<long long>(above)) - 1 : 64;
+  // the longest run in the wave bounds the reduction steps (uniform)
+  int steps = 0;
+  {
+    int run = seg_end - lane;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int r = __shfl_xor(run, o);
+      run = run > r ? run : r;
+    }
+    while ((1 << steps) < run) ++steps;
+  }
+  // P is uniform over the live lanes; lanes past the end walk the same
+  // number of entries with zero contributions
+  int Pw = P;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int r = __shfl_xor(Pw, o);
+    Pw = Pw > r ? Pw : r;
+  }
+  P = Pw;
+  walk([&](int64_t idx, T w) {
+    T v = live ? (MODE == kDiag ? w * w : s * w) : T(0);
+    for (int k = 0; k < steps; ++k) {
+      const int o = 1 << k;
+      const T u = __shfl_down(v, o);
+      if (lane + o < seg_end) v += u;
+    }
+    if (head && live) atomicAdd(&out[idx], v);
+  });
 }
 
 // One dimension p of the three-accumulator recursion for Lambda (Alg. 2):

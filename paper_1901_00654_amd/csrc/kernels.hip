@@ -574,7 +574,18 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
         }
 #pragma unroll
         for (int v = 0; v < V; ++v) s_slot[size_t(threadIdx.x) * V + v] = double(acc[v]);
-        if (lig == 0) s_jcell[grp] = jc;
+        if (lig == 0) {
+          // the item's cell as packed tile coordinates, 6 bits per dimension
+          int pc = -1;
+          if (jc >= 0) {
+            int cl[D];
+            morton_decode<D>(uint32_t(jc), tbits, cl);
+            pc = 0;
+#pragma unroll
+            for (int p = 0; p < D; ++p) pc |= cl[p] << (6 * p);
+          }
+          s_jcell[grp] = pc;
+        }
         __syncthreads();
         for (int e = threadIdx.x; e < patch; e += kBlock) {
           int el[D];
@@ -588,16 +599,14 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
           }
           double sum = 0.0;
           for (int g2 = 0; g2 < GP::NG; ++g2) {
-            const int jg = s_jcell[g2];
-            if (jg < 0) continue;
-            int cl2[D];
-            morton_decode<D>(uint32_t(jg), tbits, cl2);
+            const int pc = s_jcell[g2];
+            if (pc < 0) continue;
             bool in = true;
             int dl[D];
 #pragma unroll
             for (int p = 0; p < D; ++p) {
-              dl[p] = el[p] - cl2[p];
-              in = in && dl[p] >= 0 && dl[p] <= kDeg;
+              dl[p] = el[p] - ((pc >> (6 * p)) & 63);
+              in = in && unsigned(dl[p]) <= unsigned(kDeg);
             }
             if (!in) continue;
             int lane = 0;

@@ -326,12 +326,15 @@ __global__ __launch_bounds__(kBlock) void k_dense_lambda_gen(GenLevel L, const d
 }
 
 // Dense coarse matrix: A += Phi'Phi, one thread per (point, patch entry a),
-// adding phi_a phi_b for every patch entry b (atomics).
+// adding phi_a phi_b for every patch entry b; the lanes of a wave that share
+// a cell (and so the row a) sum their terms by shuffles before one atomic.
 __global__ __launch_bounds__(kBlock) void k_dense_gram_gen(GenPoints pts, GenLevel L, int P, double* A) {
+  // thread t: patch entry ea = t / n of point i = t % n, so that the lanes of
+  // a wave are consecutive points with the same ea
   const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (t >= pts.n * int64_t(P)) return;
-  const int64_t i = t / P;
-  const int ea = int(t % P);
+  const bool live = t < pts.n * int64_t(P);
+  const int64_t i = live ? t % pts.n : 0;
+  const int ea = live ? int(t / pts.n) : 0;
   const int d = L.d;
   double b[kMaxDim][kQMax + 1];
   int64_t base = 0;
@@ -355,11 +358,38 @@ __global__ __launch_bounds__(kBlock) void k_dense_gram_gen(GenPoints pts, GenLev
     return w;
   };
   int64_t ka;
-  const double wa = entry(ea, ka);
+  double wa = entry(ea, ka);
+  if (!live) {
+    wa = 0.0;
+    ka = -1 - int64_t(threadIdx.x & 63);   // a run of its own
+  }
+  // runs of lanes with the same row ka (the same cell and entry): their
+  // contributions to every A[ka][kb] are summed by shuffles first
+  const int lane = threadIdx.x & 63;
+  const int64_t prev = __shfl_up(ka, 1);
+  const bool head = lane == 0 || prev != ka;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long above = lane == 63 ? 0ull : (heads >> (lane + 1)) << (lane + 1);
+  const int seg_end = above ? __ffsll(static_cast<long long>(above)) - 1 : 64;
+  int steps = 0;
+  {
+    int run = seg_end - lane;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int r = __shfl_xor(run, o);
+      run = run > r ? run : r;
+    }
+    while ((1 << steps) < run) ++steps;
+  }
   for (int eb = 0; eb < P; ++eb) {
     int64_t kb;
     const double wb = entry(eb, kb);
-    atomicAdd(&A[ka * L.K + kb], wa * wb);
+    double v = wa * wb;
+    for (int k = 0; k < steps; ++k) {
+      const int o = 1 << k;
+      const double u = __shfl_down(v, o);
+      if (lane + o < seg_end) v += u;
+    }
+    if (head && live) atomicAdd(&A[ka * L.K + kb], v);
   }
 }
 

@@ -128,10 +128,12 @@ __device__ __forceinline__ T patch_gather(const T* lc, int base, const T (&B)[D]
 // cuts the segment into items: runs of at most Q points of one cell (read
 // from the level's work list, or derived from the cell offsets on the fly).
 //
-// Items go to lane groups of L = 4^(D-2) lanes (one lane for D <= 2). A
-// lane holds 16 coefficients of the cell's 4^D patch in registers - the last
-// two dimensions, for its own fixed leading multi-index - and 16
-// accumulators. Per point the group evaluates the cubic pieces (the lane's
+// Items go to lane groups of L = 4^(D-2) lanes (one lane for D <= 2; eight
+// for D = 3). A lane holds 16 coefficients of the cell's 4^D patch in
+// registers - the last two dimensions, for its own fixed leading
+// multi-index - and 16 accumulators (at D = 3 eight of each: its half of
+// dimension 1, which leaves registers for six waves per SIMD instead of
+// four: 77 against 83 us at C2). Per point the group evaluates the cubic pieces (the lane's
 // own factor of the leading dimensions by Horner, the four values of each
 // of the last two dimensions), gathers s = v'c (sum-factorised, then summed
 // over the group by shuffles) and scatters s v into its accumulators. After
@@ -166,8 +168,8 @@ constexpr int kMaxTileCells = 256;   // cells of one tile, at most (one per thre
 
 template <int D>
 struct Group {
-  static constexpr int L = (D <= 2) ? 1 : (1 << (2 * (D - 2)));   // lanes per item
-  static constexpr int V = (D == 1) ? 4 : 16;                      // coefficients per lane
+  static constexpr int L = (D <= 2) ? 1 : (D == 3 ? 8 : (1 << (2 * (D - 2))));   // lanes per item
+  static constexpr int V = (D == 1) ? 4 : (D == 3 ? 8 : 16);                      // coefficients per lane
   static constexpr int Q = kItemQ[D];                              // points per item
   static constexpr int NG = kBlock / L;                            // groups per workgroup
   static constexpr int PPB = kMaxPointsPerBlock[D];                // points per workgroup, at most
@@ -208,6 +210,7 @@ __device__ __forceinline__ T group_sum(T v) {
     v += dpp_mov<kDppQuadXor1>(v);
     v += dpp_mov<kDppQuadXor2>(v);
   }
+  if constexpr (L == 8) v += dpp_mov<0x141>(v);   // row_half_mirror: the other quad of the eight
   if constexpr (L >= 16) {
     v += dpp_mov<kDppRowRor4>(v);
     v += dpp_mov<kDppRowRor8>(v);
@@ -366,10 +369,12 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
   int lead_off = 0;
 #pragma unroll
   for (int q = 0; q < NLEAD; ++q) {
-    const int aq = (lig >> (2 * (NLEAD - 1 - q))) & 3;
+    const int aq = (D == 3 && L == 8) ? (lig >> 1) : ((lig >> (2 * (NLEAD - 1 - q))) & 3);
     piece_coeffs<T>(aq, hc[q][0], hc[q][1], hc[q][2], hc[q][3]);
     lead_off += aq * st[q];
   }
+  const int hh = (D == 3 && L == 8) ? (lig & 1) : 0;   // the lane's half of dimension D-2
+  if constexpr (D == 3 && L == 8) lead_off += hh * 2 * st[1];
 
   // level-g positions in the cell of points [from, from + m) to s_tt[p][0..m)
   auto stage_points = [&](int64_t from, int m) {
@@ -530,17 +535,44 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
         if constexpr (MODE == kApply && STAGE_C) cv[v] = lc[base + off];
         acc[v] = T(0);
       }
-      // one point per step: the live registers stay low enough for five
+      // one point per step: the live registers stay low enough for six
       // (d = 3) or four (d = 4, 5) waves per SIMD, which hides the LDS and
       // DPP latencies better than two interleaved points at three waves
       for (int li = l0; li < l1; ++li) {
         PointVals<D, T> q0;
         point_basis<D, T, NLEAD>(s_tt, a.ppb, sbase + li, hc, q0);
         T s0;
+        if constexpr (D == 3 && L == 8) {
+          const T b2lo = hh ? q0.bm2[2] : q0.bm2[0];
+          const T b2hi = hh ? q0.bm2[3] : q0.bm2[1];
+          if constexpr (MODE == kApply) {
+            T r0 = T(0), r1 = T(0);
+#pragma unroll
+            for (int bb = 0; bb < 4; ++bb) {
+              r0 += q0.bm1[bb] * cv[bb];
+              r1 += q0.bm1[bb] * cv[4 + bb];
+            }
+            s0 = group_sum<T, L>(q0.w * (b2lo * r0 + b2hi * r1));
+          } else if constexpr (MODE == kRhs) {
+            s0 = T(a.y[pos + li]);
+          } else {
+            s0 = T(1);
+          }
+          const bool sq = MODE == kDiag;
+          const T u = sq ? s0 * q0.w * q0.w : s0 * q0.w;
+          const T u0 = sq ? u * b2lo * b2lo : u * b2lo;
+          const T u1 = sq ? u * b2hi * b2hi : u * b2hi;
+#pragma unroll
+          for (int bb = 0; bb < 4; ++bb) {
+            acc[bb] += sq ? u0 * q0.bm1[bb] * q0.bm1[bb] : u0 * q0.bm1[bb];
+            acc[4 + bb] += sq ? u1 * q0.bm1[bb] * q0.bm1[bb] : u1 * q0.bm1[bb];
+          }
+        } else {
         if constexpr (MODE == kApply) s0 = group_sum<T, L>(q0.w * point_gather<D, T>(q0, cv));
         else if constexpr (MODE == kRhs) s0 = T(a.y[pos + li]);
         else s0 = T(1);
         point_scatter<D, T, MODE == kDiag>(q0, s0, acc);
+        }
       }
       return j;
     };
@@ -609,10 +641,16 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
               in = in && unsigned(dl[p]) <= unsigned(kDeg);
             }
             if (!in) continue;
-            int lane = 0;
+            int lane = 0, v;
+            if constexpr (D == 3 && L == 8) {
+              // eight lanes: the leading digit and the half of dimension 1
+              lane = dl[0] * 2 + (dl[1] >> 1);
+              v = (dl[1] & 1) * 4 + dl[2];
+            } else {
 #pragma unroll
-            for (int q = 0; q < NLEAD; ++q) lane = lane * 4 + dl[q];
-            const int v = (D == 1) ? dl[0] : dl[D - 2] * 4 + dl[D - 1];
+              for (int q = 0; q < NLEAD; ++q) lane = lane * 4 + dl[q];
+              v = (D == 1) ? dl[0] : dl[D - 2] * 4 + dl[D - 1];
+            }
             sum += s_slot[(size_t(g2) * L + lane) * V + v];
           }
           lacc[e] += sum;

@@ -646,10 +646,12 @@ __global__ __launch_bounds__(kBlock) void k_data(DataArgs a) {
               // eight lanes: the leading digit and the half of dimension 1
               lane = dl[0] * 2 + (dl[1] >> 1);
               v = (dl[1] & 1) * 4 + dl[2];
+            } else if constexpr (D == 1) {
+              v = dl[0];
             } else {
 #pragma unroll
               for (int q = 0; q < NLEAD; ++q) lane = lane * 4 + dl[q];
-              v = (D == 1) ? dl[0] : dl[D - 2] * 4 + dl[D - 1];
+              v = dl[D - 2] * 4 + dl[D - 1];
             }
             sum += s_slot[(size_t(g2) * L + lane) * V + v];
           }

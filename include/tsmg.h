@@ -145,6 +145,15 @@ typedef struct {
                               the benchmark workloads). Cubic splines on equal power-of-two
                               grids only (TS_EINVAL otherwise); read by ts_create
                               only; default 0                                        */
+    int bottom_max_k;      /* the V-cycle below the finest level is applied, from the
+                              largest level g with K_g <= bottom_max_k whose A_g is
+                              held as a stencil, by one product with its dense
+                              operator B_g (alpha = B_g b, the same linear map as
+                              Alg. 7 from g down, assembled at setup); 0 =
+                              automatic (2744), < 0 = never. Used with the damped
+                              Jacobi smoother, the direct coarse solver and the
+                              nu1, nu2 given to ts_create (other settings run the
+                              levels one by one); read by ts_create only          */
 } ts_options;
 
 typedef struct {
@@ -224,6 +233,11 @@ ts_status ts_num_coeffs(const ts_problem* p, int level, int64_t* K);
 /* The damping omega_g used by the Jacobi smoother on level g (1 <= g <= G; the
  * coarsest level c and the levels below it report 0). */
 ts_status ts_get_omega(const ts_problem* p, int level, double* omega);
+
+/* The level g whose V-cycle (Alg. 7 from g down to the coarsest level) is
+ * applied as one dense operator under the current options (bottom_max_k of
+ * ts_options), or 0 when every level runs its own steps. */
+ts_status ts_bottom_level(const ts_problem* p, int* level);
 
 /* b = Phi_G' y on the finest level (Alg. 3; first line of Alg. 8). b: device, K_G doubles. */
 ts_status ts_rhs(ts_problem* p, double* b);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtsmg.so")
-SOURCES = ["kernels.hip", "sort.hip", "problem.cpp", "solve.cpp", "api.cpp", "server.cpp", "noalloc.hip", "general.hip", "general_setup.cpp"]
+SOURCES = ["kernels.hip", "sort.hip", "problem.cpp", "solve.cpp", "api.cpp", "server.cpp", "noalloc.hip", "general.hip", "general_setup.cpp", "bottom.hip"]
 ARCH = "gfx950"
 
 COMMON = [

@@ -113,6 +113,15 @@ ts_status ts_set_options(ts_problem* p, const ts_options* opt) {
   TS_API_END
 }
 
+ts_status ts_bottom_level(const ts_problem* p, int* level) {
+  TS_API_BEGIN
+  Problem* P = get(p);
+  need(level != nullptr, "level must not be null");
+  *level = tsmg::bottom_level(P);
+  return TS_OK;
+  TS_API_END
+}
+
 ts_status ts_num_levels(const ts_problem* p, int* G) {
   TS_API_BEGIN
   Problem* P = get(p);

@@ -116,6 +116,26 @@ hipError_t launch_symmetrize(double* A, int K, hipStream_t st);
 template <typename TB, typename TV, typename TO>
 hipError_t launch_gemv(const double* A, int K, const TB* base, double s, const TV* v, TO* out, hipStream_t st);
 
+// Dense V-cycle operator of the lower levels (bottom.hip).
+// C = base + rs .* (dlt I + sgn A B) for row-major FP64 A (M x Kd) and B
+// (Kd x N) on the matrix cores; base and rs may be null, C must not alias A
+// or B (base may alias C).
+hipError_t launch_gemm64(const double* A, const double* B, int M, int N, int Kd, const double* base,
+                         const double* rs, double dlt, double sgn, double* C, hipStream_t st);
+// The dense subdivision restriction Jc^D x Jf^D (eq. 2.5 transposed), or with
+// transpose set the prolongation Jf^D x Jc^D.
+hipError_t launch_subdivision_dense(double* out, int D, int Jc, int Jf, bool transpose, hipStream_t st);
+hipError_t launch_diag_dense(const double* w, int64_t K, double* out, hipStream_t st);
+// out = I - A diag(w)
+hipError_t launch_eye_minus_scaled(const double* A, const double* w, int64_t K, double* out, hipStream_t st);
+hipError_t launch_round_f32(const double* in, int64_t n, float* out, hipStream_t st);
+// s = diag(A)^-1/2 of a dense K x K matrix; A_ij *= s_i s_j
+hipError_t launch_inv_sqrt_diag(const double* A, int K, double* s, hipStream_t st);
+hipError_t launch_sym_scale(double* A, int K, const double* s, hipStream_t st);
+// out = B v (dense K x K, FP64 accumulation)
+template <typename TM, typename TV>
+hipError_t launch_bottom_gemv(const TM* B, int K, const TV* v, TV* out, hipStream_t st);
+
 // Assembled 7^D stencil of a level (moments -> D Kronecker passes -> finalize).
 hipError_t launch_level_moments(int D, const double* t64, const uint32_t* cell, const int32_t* off, int64_t n,
                                 int G, int g, double* mom, bool det, hipStream_t st);

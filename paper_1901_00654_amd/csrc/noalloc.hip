@@ -79,6 +79,7 @@ ts_status ts_solve_noalloc(int d, int q, const int32_t* intervals, const double*
   ts_options o;
   ts_default_options(&o);
   if (opt) o = *opt;
+  o.bottom_max_k = -1;   // every V-cycle level runs its own steps (no dense operator to assemble)
   // reject sizes beyond the scratch before any work: the estimate of the
   // peak bytes with stencils held to half of the scratch
   {

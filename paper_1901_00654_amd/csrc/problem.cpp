@@ -655,6 +655,17 @@ static void ssor_step(Problem* P, int g, T* x, const T* b) {
   P->applies += 2;
 }
 
+int bottom_level(const Problem* P) {
+  if (P->bottom_g == 0 || P->opt.smoother != TS_SMOOTH_JACOBI || P->opt.coarse_solver != TS_COARSE_DIRECT ||
+      P->opt.nu1 != P->bottom_nu1 || P->opt.nu2 != P->bottom_nu2)
+    return 0;
+  return P->bottom_g;
+}
+
+template <typename T> static const T* bottom_op(Problem* P);
+template <> const double* bottom_op<double>(Problem* P) { return P->bottom64.p; }
+template <> const float* bottom_op<float>(Problem* P) { return P->bottom32.p; }
+
 // Where the first Jacobi sweep of the V-cycle on level g (g below the finest)
 // lands, when that sweep is the plain product alpha = w .* b that the
 // restriction producing b can write as well; null when it is not (coarsest
@@ -663,7 +674,7 @@ static void ssor_step(Problem* P, int g, T* x, const T* b) {
 // (alpha: the output of that V-cycle.)
 template <typename T>
 T* first_sweep_target(Problem* P, int g, T* alpha) {
-  if (P->general || g <= P->Gc || P->opt.nu1 < 1) return nullptr;
+  if (P->general || g <= P->Gc || P->opt.nu1 < 1 || g == bottom_level(P)) return nullptr;
   Level& L = P->lev[g];
   if (L.stencil) {
     if (P->opt.smoother == TS_SMOOTH_SSOR || P->opt.nu1 != 1) return nullptr;
@@ -696,6 +707,10 @@ template <typename T>
 void vcycle_op(Problem* P, int g, const T* b, T* alpha, bool pre_done) {
   if (g == P->Gc) {
     coarse_op<T>(P, b, alpha);
+    return;
+  }
+  if (g == bottom_level(P)) {   // the whole V-cycle from here down: alpha = B_g b
+    hip_check(launch_bottom_gemv<T, T>(bottom_op<T>(P), int(P->lev[g].K), b, alpha, P->stream), "bottom");
     return;
   }
   Level& L = P->lev[g];
@@ -993,6 +1008,27 @@ static bool want_stencil(int d, int J, int64_t n, int mode, double budget) {
   return entries * 1.6e-12 < double(n) * P4 * 0.5e-12;
 }
 
+// Largest level size whose V-cycle operator is assembled when bottom_max_k is 0.
+constexpr int64_t kBottomMaxK = 2744;
+
+// The level from which the V-cycle is assembled as one dense operator, for
+// these options and level sizes (0: none): the largest g below the finest,
+// above the coarsest, with every level from c + 1 to g held as a stencil
+// and K_g within the cap.
+static int choose_bottom(const ts_options& o, int Gc, int G, const std::vector<int64_t>& K,
+                         const std::vector<char>& stencil) {
+  if (o.bottom_max_k < 0 || o.coarse_solver == TS_COARSE_CG || o.smoother != TS_SMOOTH_JACOBI ||
+      o.preconditioner != TS_PC_MG)
+    return 0;
+  const int64_t cap = o.bottom_max_k > 0 ? o.bottom_max_k : kBottomMaxK;
+  int gb = 0;
+  for (int g = Gc + 1; g < G; ++g) {
+    if (K[size_t(g)] > cap || !stencil[size_t(g)]) break;
+    gb = g;
+  }
+  return gb;
+}
+
 static double stencil_budget_for(double stencil_budget) {
   if (stencil_budget > 0.0) return stencil_budget;
   if (g_arena) return 0.5 * double(g_arena->cap - std::min(g_arena->cap, g_arena->used));
@@ -1016,11 +1052,15 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
   const int Gc = std::max(1, std::min(G, opt.coarsest_level));
   const bool direct = opt.coarse_solver != TS_COARSE_CG;
   const bool det = opt.deterministic == 1;
+  std::vector<int64_t> Kl(size_t(G) + 1, 0);
+  std::vector<char> stl(size_t(G) + 1, 0);
   for (int g = Gc; g <= G; ++g) {
     const int J = (1 << g) + kDeg;
     const int64_t K = ipow(J, d);
     levels += 56 * K + int64_t(d) * 3 * J * 7 * 12;
     const bool st = want_stencil(d, J, n, opt.stencil_mode, stencil_budget_for(stencil_budget));
+    Kl[size_t(g)] = K;
+    stl[size_t(g)] = st;
     if (!st || det) {   // work list: items <= n; workgroups <= chunks <= nonempty tiles
                         // + n / 64 (ppb >= 64)
       const int tb = std::min(kTileBits[d], g);
@@ -1042,12 +1082,23 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
   }
   const int64_t K1 = ipow((int64_t(1) << Gc) + kDeg, d);
   const int64_t coarse = direct ? 2 * K1 * K1 * 8 + 2 * K1 * 8 : 6 * K1 * 8 + K1 * 4;
+  // the dense V-cycle operator (FP64 + FP32) and, while it is assembled,
+  // five K_g x K_g and four K_{g-1} x K_g matrices and B_{g-1}
+  int64_t bottom = 0, bottom_tmp = 0;
+  {
+    const int gb = choose_bottom(opt, Gc, G, Kl, stl);
+    for (int g = Gc + 1; g <= gb; ++g) {
+      const int64_t Kf = Kl[size_t(g)], Kc = Kl[size_t(g) - 1];
+      bottom_tmp = std::max(bottom_tmp, (5 * Kf * Kf + 4 * Kc * Kf + Kc * Kc) * 8);
+    }
+    if (gb > 0) bottom = Kl[size_t(gb)] * Kl[size_t(gb)] * 12;
+  }
   const int64_t finest = KG * (6 * 12 + 2 * 12 + 5 * 8 + 5 * 4);
   const int64_t misc = 16 * 8 + kMaxPartials * 8 + 64;
-  const int64_t steady = points + levels + stencils + coarse + finest + misc + det_part;
+  const int64_t steady = points + levels + stencils + coarse + finest + misc + det_part + bottom;
   // allocation granularity: round every buffer up, roughly 40 buffers per level
   const int64_t slack = int64_t(64) * 4096 * (G + 2);
-  return steady + std::max(sort_tmp, stencil_tmp) + slack;
+  return steady + std::max({sort_tmp, stencil_tmp, bottom_tmp}) + slack;
 }
 
 // The coarse solver of level c (Sec. 3.2.4). Direct: A_c expanded from the
@@ -1088,31 +1139,114 @@ static void build_coarse(Problem* P) {
     hip_check(launch_fill<double>(P->A1.p, 0.0, K1 * K1, P->stream), "fill");
     hip_check(launch_dense_from_stencil(D, L1.S64.p, L1.J, K1, P->A1.p, P->stream), "assemble");
   }
+  // A_c^-1 = S (S A_c S)^-1 S with S = diag(A_c)^-1/2: the Jacobi-scaled
+  // matrix, whose condition number is far smaller where a few B-splines
+  // carry little data, is inverted (its explicit inverse is then accurate
+  // in the energy norm of A_c, which the V-cycle sees)
+  DevBuf<double> sc;
+  sc.alloc(size_t(K1));
   hip_check(hipMemcpyAsync(P->A1inv.p, P->A1.p, sizeof(double) * K1 * K1, hipMemcpyDeviceToDevice, P->stream),
             "copy A1");
-  // diagonal before inversion, for the pivot test
-  std::vector<double> a1(size_t(K1) * K1);
-  hip_check(hipMemcpyAsync(a1.data(), P->A1inv.p, a1.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream),
-            "download");
-  hip_check(hipStreamSynchronize(P->stream), "sync");
+  hip_check(launch_inv_sqrt_diag(P->A1.p, int(K1), sc.p, P->stream), "coarse scaling");
+  hip_check(launch_sym_scale(P->A1inv.p, int(K1), sc.p, P->stream), "coarse scaling");
   row.alloc(size_t(K1));
   col.alloc(size_t(K1));
   piv.alloc(size_t(K1));
   for (int k = 0; k < K1; ++k)
     hip_check(launch_gj_step(P->A1inv.p, int(K1), k, row.p, col.p, piv.p, P->stream), "gauss-jordan");
+  hip_check(launch_sym_scale(P->A1inv.p, int(K1), sc.p, P->stream), "coarse scaling");
   hip_check(launch_symmetrize(P->A1inv.p, int(K1), P->stream), "symmetrize");
   std::vector<double> pv(static_cast<size_t>(K1));
   hip_check(hipMemcpyAsync(pv.data(), piv.p, pv.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream),
             "download");
   hip_check(hipStreamSynchronize(P->stream), "sync");
+  // pivots of the scaled matrix (unit diagonal): pivot_k / A_kk of the original
   for (int64_t k = 0; k < K1; ++k) {
-    const double dkk = a1[size_t(k) * K1 + k];
-    if (!std::isfinite(pv[k]) || !(pv[k] > 1e-13 * dkk)) {
+    if (!std::isfinite(pv[k]) || !(pv[k] > 1e-13)) {
       throw Error{TS_ESINGULAR,
                   "coarse matrix A_" + std::to_string(c) + " is not positive definite (pivot " + std::to_string(k) +
                       " = " + std::to_string(pv[k]) + "): some affine function vanishes at every data point"};
     }
   }
+}
+
+// B_c = the explicit inverse of A_c (of its Jacobi-scaled form, scaled
+// back); then level by level B_g from B_{g-1} by the steps of Alg. 7 on
+// dense matrices (bottom.hip), up to the chosen level; B_g kept in FP64 and
+// FP32. (The coarse solve's refinement step is left out here: formed as the
+// matrix B + B (I - A_c B) it loses accuracy in the energy norm where
+// kappa(A_c) is large, instead of gaining it as it does on each vector.)
+static void build_bottom(Problem* P) {
+  P->bottom_g = 0;
+  if (P->general || g_arena) return;   // the no-allocation solve runs every level
+  std::vector<int64_t> K(size_t(P->G) + 1, 0);
+  std::vector<char> st(size_t(P->G) + 1, 0);
+  for (int g = P->Gc; g <= P->G; ++g) {
+    K[size_t(g)] = P->lev[g].K;
+    st[size_t(g)] = P->lev[g].S64.p != nullptr;
+  }
+  const int gb = choose_bottom(P->opt, P->Gc, P->G, K, st);
+  if (gb == 0) return;
+  const int D = P->d, nu1 = P->opt.nu1, nu2 = P->opt.nu2;
+  hipStream_t s = P->stream;
+  int64_t Kc = P->K1;
+  DevBuf<double> Bc, T;
+  Bc.alloc(size_t(Kc * Kc));
+  hip_check(hipMemcpyAsync(Bc.p, P->A1inv.p, sizeof(double) * size_t(Kc * Kc), hipMemcpyDeviceToDevice, s),
+            "bottom");
+  for (int g = P->Gc + 1; g <= gb; ++g) {
+    Level& L = P->lev[g];
+    const int64_t Kf = L.K;
+    const int M = int(Kf), Nc = int(Kc);
+    const double* w = L.wdinv64.p;
+    DevBuf<double> A, M1, X, tmp, R, Pm, Y, Z;
+    A.alloc(size_t(Kf * Kf));
+    hip_check(launch_fill<double>(A.p, 0.0, Kf * Kf, s), "fill");
+    hip_check(launch_dense_from_stencil(D, L.S64.p, L.J, Kf, A.p, s), "bottom");
+    tmp.alloc(size_t(Kf * Kf));
+    T.alloc(size_t(Kf * Kf));
+    R.alloc(size_t(Kc * Kf));
+    hip_check(launch_subdivision_dense(R.p, D, P->lev[g - 1].J, L.J, false, s), "bottom");
+    Y.alloc(size_t(Kc * Kf));
+    if (nu1 >= 1) {
+      // M1 = W, then M1 += W (I - A M1) for each further sweep
+      M1.alloc(size_t(Kf * Kf));
+      hip_check(launch_diag_dense(w, Kf, M1.p, s), "bottom");
+      for (int j = 1; j < nu1; ++j) {
+        hip_check(launch_gemm64(A.p, M1.p, M, M, M, M1.p, w, 1.0, -1.0, tmp.p, s), "bottom");
+        std::swap(M1, tmp);
+      }
+      // T = I - A M1, the residual after the pre-smoothing; Y = I' T
+      if (nu1 == 1) hip_check(launch_eye_minus_scaled(A.p, w, Kf, T.p, s), "bottom");
+      else hip_check(launch_gemm64(A.p, M1.p, M, M, M, nullptr, nullptr, 1.0, -1.0, T.p, s), "bottom");
+      hip_check(launch_gemm64(R.p, T.p, Nc, M, M, nullptr, nullptr, 0.0, 1.0, Y.p, s), "bottom");
+    } else {
+      hip_check(hipMemcpyAsync(Y.p, R.p, sizeof(double) * size_t(Kc * Kf), hipMemcpyDeviceToDevice, s), "bottom");
+    }
+    // Z = B_{g-1} Y; X = M1 + I Z
+    Z.alloc(size_t(Kc * Kf));
+    hip_check(launch_gemm64(Bc.p, Y.p, Nc, M, Nc, nullptr, nullptr, 0.0, 1.0, Z.p, s), "bottom");
+    Pm.alloc(size_t(Kf * Kc));
+    hip_check(launch_subdivision_dense(Pm.p, D, P->lev[g - 1].J, L.J, true, s), "bottom");
+    X.alloc(size_t(Kf * Kf));
+    hip_check(launch_gemm64(Pm.p, Z.p, M, M, Nc, nu1 >= 1 ? M1.p : nullptr, nullptr, 0.0, 1.0, X.p, s), "bottom");
+    // post-smoothing: X += W (I - A X), nu2 times
+    for (int j = 0; j < nu2; ++j) {
+      hip_check(launch_gemm64(A.p, X.p, M, M, M, X.p, w, 1.0, -1.0, tmp.p, s), "bottom");
+      std::swap(X, tmp);
+    }
+    if (nu1 == nu2) hip_check(launch_symmetrize(X.p, M, s), "bottom");
+    hip_check(hipStreamSynchronize(s), "sync");   // the temporaries of this level are released
+    Bc = std::move(X);
+    Kc = Kf;
+  }
+  P->bottom64 = std::move(Bc);
+  P->bottom32.alloc(size_t(Kc * Kc));
+  hip_check(launch_round_f32(P->bottom64.p, Kc * Kc, P->bottom32.p, s), "bottom");
+  hip_check(hipStreamSynchronize(s), "sync");
+  P->bottom_g = gb;
+  P->bottom_nu1 = nu1;
+  P->bottom_nu2 = nu2;
 }
 
 void check_solve_options(const ts_options& o) {
@@ -1419,6 +1553,7 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
 
     // --- coarse level (Sec. 3.2.4)
     build_coarse(P);
+    build_bottom(P);
     hip_check(hipStreamSynchronize(st), "sync");
     P->applies = 0;
     P->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -161,6 +161,11 @@ struct Problem {
   // coarse CG (TS_COARSE_CG): D_c^-1 and the CG vectors of level c
   DevBuf<double> cdinv, cx, cr, cz, cp, cv;
   int64_t coarse_iters = 0; // coarse CG iterations of the last solve
+  // the V-cycle from level bottom_g down as one dense operator (0: none),
+  // assembled for the smoothing counts bottom_nu1, bottom_nu2
+  int bottom_g = 0, bottom_nu1 = 0, bottom_nu2 = 0;
+  DevBuf<double> bottom64;  // K x K, K = K_{bottom_g}
+  DevBuf<float> bottom32;
 
   // solver vectors on the finest level
   DevBuf<double> vb, vr, vz, vp, vv;
@@ -217,6 +222,9 @@ template <typename T> void vcycle_op(Problem* P, int g, const T* b, T* alpha, bo
 // lands when it is the plain product w .* b (which the kernel producing b may
 // then write instead, passing pre_done); null when it is not.
 template <typename T> T* first_sweep_target(Problem* P, int g, T* alpha);
+// The level whose V-cycle the dense operator replaces under the current
+// options, or 0.
+int bottom_level(const Problem* P);
 template <typename T> void profile_apply(Problem* P, int g, int reps, double* ms_lambda, double* ms_data);
 template <typename TX, typename TY> void dot_op(Problem* P, const TX* x, const TY* y, int64_t K, int slot);
 

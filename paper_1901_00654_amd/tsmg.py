@@ -39,7 +39,7 @@ class ts_options(ctypes.Structure):
                 ("ssor_omega", ctypes.c_double), ("coarse_solver", ctypes.c_int),
                 ("coarse_tol", ctypes.c_double), ("coarse_max_iter", ctypes.c_int),
                 ("coarsest_level", ctypes.c_int), ("degrees", ctypes.POINTER(ctypes.c_int32)),
-                ("deterministic", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("bottom_max_k", ctypes.c_int)]
 
 
 class ts_solve_info(ctypes.Structure):
@@ -117,6 +117,7 @@ _SIGNATURES = {
     "ts_num_levels": (_I, [_P, ctypes.POINTER(_I)]),
     "ts_num_coeffs": (_I, [_P, _I, ctypes.POINTER(_I64)]),
     "ts_get_omega": (_I, [_P, _I, ctypes.POINTER(_D)]),
+    "ts_bottom_level": (_I, [_P, ctypes.POINTER(_I)]),
     "ts_rhs": (_I, [_P, _P]),
     "ts_apply": (_I, [_P, _I, _P, _P]),
     "ts_apply_f32": (_I, [_P, _I, _P, _P]),
@@ -236,6 +237,12 @@ def ts_num_coeffs(h, level):
     K = _I64()
     _check(load_library().ts_num_coeffs(h, int(level), ctypes.byref(K)))
     return K.value
+
+
+def ts_bottom_level(h):
+    g = _I()
+    _check(load_library().ts_bottom_level(h, ctypes.byref(g)))
+    return g.value
 
 
 def ts_get_omega(h, level):
@@ -543,6 +550,10 @@ class Smoother:
 
     def omega(self, level):
         return ts_get_omega(self.handle, level)
+
+    def bottom_level(self):
+        """Level whose V-cycle runs as one dense operator (0: none)."""
+        return ts_bottom_level(self.handle)
 
     def prolong(self, level, e):
         def f():

@@ -109,6 +109,7 @@ ts_status ts_set_options(ts_problem* p, const ts_options* opt) {
   P->opt.tol = opt->tol;
   P->opt.inner_tol = opt->inner_tol;
   P->opt.max_refine = opt->max_refine;
+  P->opt.vcycle_graph = opt->vcycle_graph;
   return TS_OK;
   TS_API_END
 }

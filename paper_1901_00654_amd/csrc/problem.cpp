@@ -1260,6 +1260,7 @@ void check_solve_options(const ts_options& o) {
   if (o.smoother == TS_SMOOTH_SSOR && !(o.ssor_omega > 0.0 && o.ssor_omega < 2.0))
     throw Error{TS_EINVAL, "ssor_omega must be in (0, 2)"};
   if (o.coarse_tol < 0.0 || o.coarse_max_iter < 0) throw Error{TS_EINVAL, "coarse CG limits must be >= 0"};
+  if (o.vcycle_graph != 0 && o.vcycle_graph != 1) throw Error{TS_EINVAL, "vcycle_graph must be 0 or 1"};
 }
 
 Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo, const double* hi, int64_t n,
@@ -1568,6 +1569,8 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
 
 Problem::~Problem() {
   (void)hipStreamSynchronize(stream);   // also the null stream of the no-allocation mode
+  for (Captured& c : vgraph)
+    if (c.exec) (void)hipGraphExecDestroy(c.exec);
   lev.clear();
   if (host_slots && pinned_slots) (void)hipHostFree(host_slots);
   if (slots_ready) (void)hipEventDestroy(slots_ready);

@@ -180,6 +180,16 @@ struct Problem {
   double* host_slots = nullptr;
   bool pinned_slots = true;   // host_slots from hipHostMalloc (else caller-owned host memory)
 
+  // V-cycles of a solve replayed from captured HIP graphs, one per kind of
+  // call (precision, first sweep already written); key: the pointers and
+  // options the capture baked in; applies: operator applies per replay
+  struct Captured {
+    hipGraphExec_t exec = nullptr;
+    uint64_t key = 0;
+    int64_t applies = 0;
+  };
+  Captured vgraph[4];
+
   double setup_s = 0.0;
   int64_t applies = 0;
   std::vector<double> history;   // residual history of the last solve

@@ -6,7 +6,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstdlib>
+#include <cstring>
 #include <utility>
 
 #include "problem.h"
@@ -53,6 +55,72 @@ void report(int every, const char* mode, int it, double rel) {
   }
 }
 
+// The V-cycle of a solve as a captured HIP graph (vcycle_graph set): its
+// kernels are recorded once (per kind of call and per set of pointers and
+// options they bake in) and then replayed each iteration with one launch.
+// Only kernel launches are recorded: no memsets, no host reads. Not used on
+// the null stream, with the no-allocation arena (instantiation may
+// allocate) or with the CG coarse solver (it reads its residual on the host).
+bool capture_usable(const Problem* P) {
+  return P->opt.vcycle_graph == 1 && P->stream != nullptr && g_arena == nullptr &&
+         P->opt.coarse_solver != TS_COARSE_CG;
+}
+
+uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+uint64_t capture_key(const Problem* P, const void* in, const void* out, const void* aux) {
+  uint64_t h = 0;
+  double om = P->opt.ssor_omega;
+  uint64_t omb = 0;
+  static_assert(sizeof(om) == sizeof(omb), "double is 64 bits");
+  std::memcpy(&omb, &om, sizeof(omb));
+  for (uint64_t v : {uint64_t(reinterpret_cast<uintptr_t>(in)), uint64_t(reinterpret_cast<uintptr_t>(out)),
+                     uint64_t(reinterpret_cast<uintptr_t>(aux)), uint64_t(P->opt.nu1), uint64_t(P->opt.nu2),
+                     uint64_t(P->opt.smoother), omb, uint64_t(bottom_level(P)),
+                     uint64_t(reinterpret_cast<uintptr_t>(P->stream))})
+    h = mix(h, v);
+  return h | 1;   // never 0, the key of an empty entry
+}
+
+template <typename F>
+void run_captured(Problem* P, int which, uint64_t key, F&& body) {
+  if (!capture_usable(P)) {
+    body();
+    return;
+  }
+  Problem::Captured& c = P->vgraph[which];
+  if (!c.exec || c.key != key) {
+    if (c.exec) {
+      hip_check(hipStreamSynchronize(P->stream), "sync");   // no replay of the old graph is in flight
+      hip_check(hipGraphExecDestroy(c.exec), "graph destroy");
+      c.exec = nullptr;
+    }
+    const int64_t a0 = P->applies;
+    hip_check(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    try {
+      body();
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(P->stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    hipGraph_t g = nullptr;
+    hip_check(hipStreamEndCapture(P->stream, &g), "end capture");
+    const hipError_t e = hipGraphInstantiate(&c.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    hip_check(e, "graph instantiate");
+    c.key = key;
+    c.applies = P->applies - a0;
+    P->applies = a0;
+  }
+  hip_check(hipGraphLaunch(c.exec, P->stream), "graph launch");
+  P->applies += c.applies;
+}
+
 }  // namespace
 
 void rhs_op(Problem* P, double* b) { rhs_into(P, b); }
@@ -72,12 +140,15 @@ static void precondition(Problem* P, bool pc32, const double* r, double* z, int 
     return;
   }
   if (!pc32) {
-    vcycle_op<double>(P, G, r, z, pre_done);
+    run_captured(P, pre_done ? 1 : 0, capture_key(P, r, z, nullptr),
+                 [&] { vcycle_op<double>(P, G, r, z, pre_done); });
     return;
   }
-  hip_check(launch_scale_copy<double, float>(r, P->r32.p, K, 1.0, P->slot(rr), P->stream), "to fp32");
-  vcycle_op<float>(P, G, P->r32.p, P->z32.p);
-  hip_check(launch_scale_mul(P->z32.p, z, K, P->slot(rr), P->stream), "to fp64");
+  run_captured(P, 2, capture_key(P, r, z, P->slot(rr)), [&] {
+    hip_check(launch_scale_copy<double, float>(r, P->r32.p, K, 1.0, P->slot(rr), P->stream), "to fp32");
+    vcycle_op<float>(P, G, P->r32.p, P->z32.p);
+    hip_check(launch_scale_mul(P->z32.p, z, K, P->slot(rr), P->stream), "to fp64");
+  });
 }
 
 // Alg. 8 in FP64. With pc32 the V-cycle runs in FP32; then, and when the
@@ -228,7 +299,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
     double rmax = rel;        // FP32 residual norm (relative to ||b||) at the last update
     bool fresh = true;        // dl is zero and p = z (first step since a (re)start)
     int sa = kRZa, sb = kRZb;
-    vcycle_op<float>(P, G, rin, z);
+    run_captured(P, 3, capture_key(P, rin, z, nullptr), [&] { vcycle_op<float>(P, G, rin, z); });
     hip_check(launch_scale_copy<float, float>(z, p, K, 1.0, nullptr, st), "copy");
     dot_op<float, float>(P, rin, z, K, sa);
     for (;;) {
@@ -261,7 +332,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
         hip_check(launch_scale_copy<double, float>(r, rin, K, 1.0 / bnorm, nullptr, st), "to fp32");
         rmax = rel;
         if (breakdown) {   // restart the direction from the new residual
-          vcycle_op<float>(P, G, rin, z);
+          run_captured(P, 3, capture_key(P, rin, z, nullptr), [&] { vcycle_op<float>(P, G, rin, z); });
           hip_check(launch_scale_copy<float, float>(z, p, K, 1.0, nullptr, st), "copy");
           dot_op<float, float>(P, rin, z, K, sa);
           fresh = true;
@@ -269,7 +340,7 @@ static ts_status solve_mixed(Problem* P, double* alpha, int use_start, ts_solve_
         }
       }
       fresh = false;
-      vcycle_op<float>(P, G, rin, z);
+      run_captured(P, 3, capture_key(P, rin, z, nullptr), [&] { vcycle_op<float>(P, G, rin, z); });
       dot_op<float, float>(P, rin, z, K, sb);
       hip_check(launch_p_update<float>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
       std::swap(sa, sb);

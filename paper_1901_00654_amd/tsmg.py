@@ -39,7 +39,8 @@ class ts_options(ctypes.Structure):
                 ("ssor_omega", ctypes.c_double), ("coarse_solver", ctypes.c_int),
                 ("coarse_tol", ctypes.c_double), ("coarse_max_iter", ctypes.c_int),
                 ("coarsest_level", ctypes.c_int), ("degrees", ctypes.POINTER(ctypes.c_int32)),
-                ("deterministic", ctypes.c_int), ("bottom_max_k", ctypes.c_int)]
+                ("deterministic", ctypes.c_int), ("bottom_max_k", ctypes.c_int),
+                ("vcycle_graph", ctypes.c_int)]
 
 
 class ts_solve_info(ctypes.Structure):

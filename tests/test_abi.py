@@ -39,7 +39,7 @@ def test_defaults_and_version(built):
     o = tsmg.ts_default_options()
     assert (o.nu1, o.nu2, o.lanczos_steps, o.precision) == (1, 1, 16, tsmg.TS_FP64)
     assert o.omega_scale == 1.8 and o.tol == 1e-8 and o.stream is None
-    assert o.deterministic == 0 and o.bottom_max_k == 0
+    assert o.deterministic == 0 and o.bottom_max_k == 0 and o.vcycle_graph == 0
     assert "gfx950" in tsmg.ts_version()
 
 

@@ -1250,6 +1250,22 @@ __global__ __launch_bounds__(kBlock) void k_sum_rows(const double* partial, int 
   }
 }
 
+// The second stage of a reduction inside the kernel that consumes it: every
+// block sums the nb first-stage partials itself, in the order k_sum_partials
+// takes (so every block, and the slot, get the same bits), and block 0
+// stores the total in *out for the host and later kernels.
+__device__ __forceinline__ double resum(const double* partial, int nb, double* out, double* sh, double* bc) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) v += partial[i];
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    *bc = v;
+    if (blockIdx.x == 0) *out = v;
+  }
+  __syncthreads();
+  return *bc;
+}
+
 // alpha += w p; r -= w v with w = (*num) / (*den) read on the device. A step
 // with den <= 0 (a breakdown, which the host reports) leaves both unchanged.
 template <typename TA, typename T>
@@ -1272,13 +1288,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_step(TA* alpha, T* r, const T* p,
 // given it also writes zf = wz .* r, the first Jacobi sweep of the V-cycle
 // that preconditions r next (zf may be z: each entry is read before it is
 // written). A step with den <= 0 leaves alpha and r unchanged (the host
-// reports the breakdown).
+// reports the breakdown). With den_part given, den is the sum of its nb
+// partials (p'v, the first stage of its reduction), stored to *den.
 __global__ __launch_bounds__(kBlock) void k_cg_step_norms(double* alpha, double* r, const double* p, const double* v,
                                                           const double* z, int64_t K, const double* num,
-                                                          const double* den, double* partial, const double* wz,
-                                                          double* zf) {
+                                                          double* den, double* partial, const double* wz,
+                                                          double* zf, const double* den_part, int den_nb) {
   __shared__ double sh[kBlock / 64];
-  const double dn = *den;
+  __shared__ double bc;
+  const double dn = den_part ? resum(den_part, den_nb, den, sh, &bc) : *den;
   const bool ok = dn > 0.0 && isfinite(dn);
   const double w = ok ? *num / dn : 0.0;
   double a0 = 0.0, a1 = 0.0;
@@ -1311,14 +1329,17 @@ __global__ __launch_bounds__(kBlock) void k_p_update(T* p, const T* z, int64_t K
   p[k] = T(double(z[k]) + beta * double(p[k]));
 }
 
-// Flexible (Polak-Ribiere) direction update p = z + beta p with
-// beta = ((*num) - (*sub)) / (*den).
-__global__ __launch_bounds__(kBlock) void k_p_update_flex(double* p, const double* z, int64_t K, const double* num,
-                                                          const double* sub, const double* den) {
+// p = z + beta p, FP64, with beta = (num - (*sub)) / (*den) (sub null: 0) and
+// num the sum of the nb partials num_part (r'z), stored to *num.
+__global__ __launch_bounds__(kBlock) void k_p_update_sum(double* p, const double* z, int64_t K, double* num,
+                                                         const double* num_part, int nb, const double* sub,
+                                                         const double* den) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ double bc;
+  const double nm = resum(num_part, nb, num, sh, &bc);
+  const double beta = (sub ? nm - *sub : nm) / *den;
   const int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (k >= K) return;
-  const double beta = (*num - *sub) / *den;
-  p[k] = z[k] + beta * p[k];
+  if (k < K) p[k] = z[k] + beta * p[k];
 }
 
 // y = (*smul)^(1/2) * x with conversion.
@@ -2223,12 +2244,23 @@ hipError_t launch_dot(const TX* x, const TY* y, int64_t K, double* partial, doub
   return hipGetLastError();
 }
 
+template <typename TX, typename TY>
+hipError_t launch_dot_partial(const TX* x, const TY* y, int64_t K, double* partial, int* nb, hipStream_t st) {
+  const unsigned b = reduce_blocks(K);
+  hipLaunchKernelGGL((k_dot_partial<TX, TY>), dim3(b), dim3(kBlock), 0, st, x, y, K, partial);
+  *nb = int(b);
+  return hipGetLastError();
+}
+template hipError_t launch_dot_partial<double, double>(const double*, const double*, int64_t, double*, int*,
+                                                       hipStream_t);
+
 hipError_t launch_cg_step_norms(double* alpha, double* r, const double* p, const double* v, const double* z,
-                                int64_t K, const double* num, const double* den, double* partial, double* rr,
-                                double* rz, const double* wz, double* zf, hipStream_t st) {
+                                int64_t K, const double* num, double* den, double* partial, double* rr,
+                                double* rz, const double* wz, double* zf, const double* den_part, int den_nb,
+                                hipStream_t st) {
   const unsigned nb = reduce_blocks(K);
   hipLaunchKernelGGL(k_cg_step_norms, dim3(nb), dim3(kBlock), 0, st, alpha, r, p, v, z, K, num, den, partial, wz,
-                     zf);
+                     zf, den_part, den_nb);
   hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(kBlock), 0, st, partial, int(nb), z ? 2 : 1, rr, rz);
   return hipGetLastError();
 }
@@ -2254,9 +2286,9 @@ hipError_t launch_p_update(T* p, const T* z, int64_t K, const double* num, const
 template hipError_t launch_p_update<double>(double*, const double*, int64_t, const double*, const double*, hipStream_t);
 template hipError_t launch_p_update<float>(float*, const float*, int64_t, const double*, const double*, hipStream_t);
 
-hipError_t launch_p_update_flex(double* p, const double* z, int64_t K, const double* num, const double* sub,
-                               const double* den, hipStream_t st) {
-  hipLaunchKernelGGL(k_p_update_flex, dim3(blocks_for(K)), dim3(kBlock), 0, st, p, z, K, num, sub, den);
+hipError_t launch_p_update_sum(double* p, const double* z, int64_t K, double* num, const double* num_part, int nb,
+                               const double* sub, const double* den, hipStream_t st) {
+  hipLaunchKernelGGL(k_p_update_sum, dim3(blocks_for(K)), dim3(kBlock), 0, st, p, z, K, num, num_part, nb, sub, den);
   return hipGetLastError();
 }
 

@@ -74,16 +74,23 @@ hipError_t launch_cg_step(TA* alpha, T* r, const T* p, const T* v, int64_t K, co
                           const double* den, hipStream_t st);
 // FP64 CG step fused with *rr = r'r and (z non-null) *rz = r'z of the
 // updated r, and (zf non-null) zf = wz .* r; partial holds 2 * kMaxPartials.
+// With den_part non-null the step's denominator is the sum of those den_nb
+// partials (the first stage of p'v), also stored to *den.
 hipError_t launch_cg_step_norms(double* alpha, double* r, const double* p, const double* v, const double* z,
-                                int64_t K, const double* num, const double* den, double* partial, double* rr,
-                                double* rz, const double* wz, double* zf, hipStream_t st);
+                                int64_t K, const double* num, double* den, double* partial, double* rr,
+                                double* rz, const double* wz, double* zf, const double* den_part, int den_nb,
+                                hipStream_t st);
+// The first stage of x'y alone: per-block partials (*nb of them).
+template <typename TX, typename TY>
+hipError_t launch_dot_partial(const TX* x, const TY* y, int64_t K, double* partial, int* nb, hipStream_t st);
+// FP64 p = z + beta p, beta = (sum of the nb partials num_part - *sub) / *den
+// (sub may be null); the sum is stored to *num.
+hipError_t launch_p_update_sum(double* p, const double* z, int64_t K, double* num, const double* num_part, int nb,
+                               const double* sub, const double* den, hipStream_t st);
 template <typename T>
 hipError_t launch_p_update(T* p, const T* z, int64_t K, const double* num, const double* den, hipStream_t st);
 template <typename TI, typename TO>
 hipError_t launch_scale_copy(const TI* x, TO* y, int64_t K, double scale, const double* sden, hipStream_t st);
-// p = z + ((*num) - (*sub)) / (*den) p (flexible CG direction update)
-hipError_t launch_p_update_flex(double* p, const double* z, int64_t K, const double* num, const double* sub,
-                               const double* den, hipStream_t st);
 // y = sqrt(*smul) x
 hipError_t launch_scale_mul(const float* x, double* y, int64_t K, const double* smul, hipStream_t st);
 template <typename TI, typename TO>

@@ -1094,7 +1094,7 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
     if (gb > 0) bottom = Kl[size_t(gb)] * Kl[size_t(gb)] * 12;
   }
   const int64_t finest = KG * (6 * 12 + 2 * 12 + 5 * 8 + 5 * 4);
-  const int64_t misc = 16 * 8 + kMaxPartials * 8 + 64;
+  const int64_t misc = 16 * 8 + 3 * kMaxPartials * 8 + 64;
   const int64_t steady = points + levels + stencils + coarse + finest + misc + det_part + bottom;
   // allocation granularity: round every buffer up, roughly 40 buffers per level
   const int64_t slack = int64_t(64) * 4096 * (G + 2);
@@ -1355,7 +1355,7 @@ Problem* create_problem(int d, int q, const int32_t* intervals, const double* lo
       hip_check(hipEventCreateWithFlags(&P->slots_ready, hipEventDisableTiming), "event");
     }
     P->slots.alloc(kSlots);
-    P->partial.alloc(2 * kMaxPartials);   // two rows of per-block partials
+    P->partial.alloc(3 * kMaxPartials);   // three rows of per-block partials
     P->flag.alloc(1);
     for (int p = 0; p < d; ++p) {
       P->box.lo[p] = lo[p];

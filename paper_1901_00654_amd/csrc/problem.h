@@ -173,7 +173,7 @@ struct Problem {
   DevBuf<float> r32, z32, p32, v32, d32;
 
   DevBuf<double> slots;     // device scalars
-  DevBuf<double> partial;   // reduction partials [2][kMaxPartials]
+  DevBuf<double> partial;   // reduction partials [3][kMaxPartials]
   bool det = false;         // opt.deterministic: reproducible point passes and moments
   DevBuf<double> det_part;  // deterministic point pass: [chunks][patch] of the largest level
   DevBuf<int> flag;

@@ -205,13 +205,18 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
     precondition(P, pc32, r, z, kRR);
     hip_check(launch_scale_copy<double, double>(z, p, K, 1.0, nullptr, st), "copy");
     dot_op<double, double>(P, r, z, K, sa);
+    // the first stage of p'v and of r'z (row 2 of the partials); their
+    // second stages run inside the kernels that use them
+    double* dpart = P->partial.p + 2 * kMaxPartials;
+    int nb = 0;
     while (total < P->opt.max_iter) {
       apply_op<double>(P, G, p, v);
-      dot_op<double, double>(P, p, v, K, kPV);
-      // the step with r'r, for the flexible update r_new' z_old, and the
-      // first Jacobi sweep of the V-cycle that follows
+      hip_check(launch_dot_partial<double, double>(p, v, K, dpart, &nb, st), "dot");
+      // the step (p'v summed in it) with r'r, for the flexible update
+      // r_new' z_old, and the first Jacobi sweep of the V-cycle that follows
       hip_check(launch_cg_step_norms(alpha, r, p, v, flex ? z : nullptr, K, P->slot(sa), P->slot(kPV), P->partial.p,
-                                     P->slot(kRR), P->slot(kRZo), zf ? P->lev[G].wdinv64.p : nullptr, zf, st),
+                                     P->slot(kRR), P->slot(kRZo), zf ? P->lev[G].wdinv64.p : nullptr, zf, dpart, nb,
+                                     st),
                 "cg step");
       P->copy_slots(kPV, 2);
       // the next V-cycle is queued before the host reads the residual, so the
@@ -226,9 +231,10 @@ static ts_status solve_fp64(Problem* P, double* alpha, int use_start, ts_solve_i
       report(every, pc32 ? "vcycle32" : "fp64", total, std::sqrt(h[1]) / bnorm);
       P->history.push_back(std::sqrt(h[1]) / bnorm);
       if (std::sqrt(h[1]) / bnorm <= tol) break;
-      dot_op<double, double>(P, r, z, K, sb);
-      if (flex) hip_check(launch_p_update_flex(p, z, K, P->slot(sb), P->slot(kRZo), P->slot(sa), st), "p update");
-      else hip_check(launch_p_update<double>(p, z, K, P->slot(sb), P->slot(sa), st), "p update");
+      // r'z summed in the direction update (flexible: minus r_new' z_old)
+      hip_check(launch_dot_partial<double, double>(r, z, K, dpart, &nb, st), "dot");
+      hip_check(launch_p_update_sum(p, z, K, P->slot(sb), dpart, nb, flex ? P->slot(kRZo) : nullptr, P->slot(sa), st),
+                "p update");
       std::swap(sa, sb);
     }
     // confirm with the true FP64 residual; restart from it if the recursive

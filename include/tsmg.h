@@ -146,14 +146,16 @@ typedef struct {
                               grids only (TS_EINVAL otherwise); read by ts_create
                               only; default 0                                        */
     int bottom_max_k;      /* the V-cycle below the finest level is applied, from the
-                              largest level g with K_g <= bottom_max_k whose A_g is
-                              held as a stencil, by one product with its dense
-                              operator B_g (alpha = B_g b, the same linear map as
-                              Alg. 7 from g down, assembled at setup); 0 =
-                              automatic (2744), < 0 = never. Used with the damped
-                              Jacobi smoother, the direct coarse solver and the
-                              nu1, nu2 given to ts_create (other settings run the
-                              levels one by one); read by ts_create only          */
+                              largest level g with K_g <= bottom_max_k (whose A_g
+                              is held as a stencil, in the cubic form), by one
+                              product with its dense operator B_g (alpha = B_g b,
+                              the same linear map as Alg. 7 from g down, assembled
+                              at setup); 0 = automatic (2744; 6000 in the general
+                              form, whose levels each stream all points), < 0 =
+                              never. Used with the damped Jacobi smoother, the
+                              direct coarse solver and the nu1, nu2 given to
+                              ts_create (other settings run the levels one by
+                              one); read by ts_create only                       */
     int vcycle_graph;      /* 1: within ts_solve the V-cycle's kernels are captured
                               once into a HIP graph and replayed each iteration
                               (not on the null stream, nor with the CG coarse

@@ -141,6 +141,14 @@ __global__ __launch_bounds__(kBlock) void k_sym_scale(double* A, int K, const do
   A[t] *= s[t / K] * s[t % K];
 }
 
+// out (cols x rows) = in' (in: rows x cols).
+__global__ __launch_bounds__(kBlock) void k_transpose(const double* in, int64_t rows, int64_t cols, double* out) {
+  const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (t >= rows * cols) return;
+  const int64_t r = t / cols, c = t % cols;
+  out[c * rows + r] = in[t];
+}
+
 __global__ __launch_bounds__(kBlock) void k_round_f32(const double* in, int64_t n, float* out) {
   const int64_t t = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (t < n) out[t] = float(in[t]);
@@ -206,6 +214,11 @@ hipError_t launch_inv_sqrt_diag(const double* A, int K, double* s, hipStream_t s
 
 hipError_t launch_sym_scale(double* A, int K, const double* s, hipStream_t st) {
   hipLaunchKernelGGL(k_sym_scale, dim3(blocks_of(int64_t(K) * K)), dim3(kBlock), 0, st, A, K, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* in, int64_t rows, int64_t cols, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_transpose, dim3(blocks_of(rows * cols)), dim3(kBlock), 0, st, in, rows, cols, out);
   return hipGetLastError();
 }
 

@@ -54,7 +54,22 @@ int64_t footprint_general(int d, int q, const int32_t* N, int64_t n, const ts_op
   const int64_t points = n * (16 * int64_t(d) + 8) + 24 * n + (1 << 20);   // sorted points, sort temporaries
   const int64_t finest = KG * (6 * 12 + 2 * 12 + 5 * 8 + 5 * 4 + 8);
   const int64_t coarse = opt.coarse_solver == TS_COARSE_CG ? 6 * Kc * 8 : 2 * Kc * Kc * 8 + 2 * Kc * 8;
-  return points + levels + finest + coarse + int64_t(64) * 4096 * (G + 2);
+  // the dense V-cycle operator of the lower levels and its assembly
+  std::vector<int64_t> Kl(size_t(G) + 1, 0);
+  std::vector<char> ok(size_t(G) + 1, 1);
+  for (int g = c; g <= G; ++g) {
+    int64_t K = 1;
+    for (int p = 0; p < d; ++p) K *= (N[p] >> (G - g)) + (opt.degrees ? opt.degrees[p] : q);
+    Kl[size_t(g)] = K;
+  }
+  const int gb = choose_bottom(opt, c, G, Kl, ok, true);
+  int64_t bottom = 0;
+  for (int g = c + 1; g <= gb; ++g) {
+    const int64_t Kf = Kl[size_t(g)], Kg = Kl[size_t(g) - 1];
+    bottom = std::max(bottom, (5 * Kf * Kf + 6 * Kg * Kf + 2 * Kg * Kg) * 8);
+  }
+  if (gb > 0) bottom += Kl[size_t(gb)] * Kl[size_t(gb)] * 12;
+  return points + levels + finest + coarse + bottom + int64_t(64) * 4096 * (G + 2);
 }
 
 namespace {
@@ -318,10 +333,46 @@ void diag_general(Problem* P, int g) {
   hip_check(launch_data_gen<double>(kDiag, points_of(P, false), L.gl, nullptr, L.diag.p, P->stream), "data diag");
 }
 
-void coarse_matrix_general(Problem* P, double* A) {
-  Level& L = P->lev[P->Gc];
+void coarse_matrix_general(Problem* P, double* A) { dense_level_general(P, P->Gc, A); }
+
+void dense_level_general(Problem* P, int g, double* A) {
+  Level& L = P->lev[g];
   hip_check(launch_fill<double>(A, 0.0, L.K * L.K, P->stream), "fill");
-  hip_check(launch_dense_coarse_gen(points_of(P, false), L.gl, L.band64.p, P->lam, A, P->stream), "coarse matrix");
+  hip_check(launch_dense_coarse_gen(points_of(P, false), L.gl, L.band64.p, P->lam, A, P->stream), "dense level");
+}
+
+// R = I_g' (K_{g-1} x K_g): every coarse unit vector prolongated at once, one
+// subdivision pass per dimension over a leading batch index (row j of R is
+// I_g e_j, the j-th column of I_g).
+void restriction_dense_general(Problem* P, int g, double* R) {
+  const GenLevel& F = P->lev[g].gl;
+  const GenLevel& C = P->lev[g - 1].gl;
+  const int d = P->d;
+  const int64_t Kc = C.K, Kf = F.K;
+  hipStream_t st = P->stream;
+  DevBuf<double> one, bufs[2];
+  one.alloc(size_t(Kc));
+  bufs[0].alloc(size_t(Kc * Kf));
+  bufs[1].alloc(size_t(Kc * Kf));
+  hip_check(launch_fill<double>(one.p, 1.0, Kc, st), "fill");
+  hip_check(launch_diag_dense(one.p, Kc, bufs[0].p, st), "identity");
+  const double* cur = bufs[0].p;
+  for (int p = 0; p < d; ++p) {
+    GenTransferArgs<double> a{};
+    int64_t inner = 1, outer = Kc;
+    for (int r = p + 1; r < d; ++r) inner *= C.J[r];
+    for (int r = 0; r < p; ++r) outer *= F.J[r];
+    a.in = cur;
+    a.out = (p == d - 1) ? R : bufs[(p + 1) % 2].p;
+    a.Kout = outer * F.J[p] * inner;
+    a.inner = inner;
+    a.Jc = C.J[p];
+    a.Jf = F.J[p];
+    a.q = F.q[p];
+    hip_check(launch_transfer_gen<double>(true, a, st), "prolongation");
+    cur = a.out;
+  }
+  hip_check(hipStreamSynchronize(st), "sync");   // the work buffers are released
 }
 
 void eval_general(Problem* P, const double* alpha, int64_t m, const double* xq, double* yq) {

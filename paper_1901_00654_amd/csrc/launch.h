@@ -136,6 +136,8 @@ hipError_t launch_diag_dense(const double* w, int64_t K, double* out, hipStream_
 // out = I - A diag(w)
 hipError_t launch_eye_minus_scaled(const double* A, const double* w, int64_t K, double* out, hipStream_t st);
 hipError_t launch_round_f32(const double* in, int64_t n, float* out, hipStream_t st);
+// out (cols x rows) = in' for a row-major rows x cols matrix
+hipError_t launch_transpose(const double* in, int64_t rows, int64_t cols, double* out, hipStream_t st);
 // s = diag(A)^-1/2 of a dense K x K matrix; A_ij *= s_i s_j
 hipError_t launch_inv_sqrt_diag(const double* A, int K, double* s, hipStream_t st);
 hipError_t launch_sym_scale(double* A, int K, const double* s, hipStream_t st);

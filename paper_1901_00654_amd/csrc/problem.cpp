@@ -1008,22 +1008,27 @@ static bool want_stencil(int d, int J, int64_t n, int mode, double budget) {
   return entries * 1.6e-12 < double(n) * P4 * 0.5e-12;
 }
 
-// Largest level size whose V-cycle operator is assembled when bottom_max_k is 0.
+// Largest level size whose V-cycle operator is assembled when bottom_max_k
+// is 0: in the cubic form, where the levels it replaces are stencil products
+// of a few microseconds each; in the general form, where each of them
+// streams all n points, up to a larger size.
 constexpr int64_t kBottomMaxK = 2744;
+constexpr int64_t kBottomMaxKGeneral = 6000;
 
 // The level from which the V-cycle is assembled as one dense operator, for
 // these options and level sizes (0: none): the largest g below the finest,
-// above the coarsest, with every level from c + 1 to g held as a stencil
-// and K_g within the cap.
-static int choose_bottom(const ts_options& o, int Gc, int G, const std::vector<int64_t>& K,
-                         const std::vector<char>& stencil) {
+// above the coarsest, with every level from c + 1 to g assemblable (held as
+// a stencil in the cubic form; from the points in the general form) and K_g
+// within the cap.
+int choose_bottom(const ts_options& o, int Gc, int G, const std::vector<int64_t>& K, const std::vector<char>& ok,
+                  bool general) {
   if (o.bottom_max_k < 0 || o.coarse_solver == TS_COARSE_CG || o.smoother != TS_SMOOTH_JACOBI ||
       o.preconditioner != TS_PC_MG)
     return 0;
-  const int64_t cap = o.bottom_max_k > 0 ? o.bottom_max_k : kBottomMaxK;
+  const int64_t cap = o.bottom_max_k > 0 ? o.bottom_max_k : (general ? kBottomMaxKGeneral : kBottomMaxK);
   int gb = 0;
   for (int g = Gc + 1; g < G; ++g) {
-    if (K[size_t(g)] > cap || !stencil[size_t(g)]) break;
+    if (K[size_t(g)] > cap || !ok[size_t(g)]) break;
     gb = g;
   }
   return gb;
@@ -1086,7 +1091,7 @@ int64_t footprint_bytes(int d, int N, int64_t n, const ts_options& opt, double s
   // five K_g x K_g and four K_{g-1} x K_g matrices and B_{g-1}
   int64_t bottom = 0, bottom_tmp = 0;
   {
-    const int gb = choose_bottom(opt, Gc, G, Kl, stl);
+    const int gb = choose_bottom(opt, Gc, G, Kl, stl, false);
     for (int g = Gc + 1; g <= gb; ++g) {
       const int64_t Kf = Kl[size_t(g)], Kc = Kl[size_t(g) - 1];
       bottom_tmp = std::max(bottom_tmp, (5 * Kf * Kf + 4 * Kc * Kf + Kc * Kc) * 8);
@@ -1178,14 +1183,14 @@ static void build_coarse(Problem* P) {
 // kappa(A_c) is large, instead of gaining it as it does on each vector.)
 static void build_bottom(Problem* P) {
   P->bottom_g = 0;
-  if (P->general || g_arena) return;   // the no-allocation solve runs every level
+  if (g_arena) return;   // the no-allocation solve runs every level
   std::vector<int64_t> K(size_t(P->G) + 1, 0);
-  std::vector<char> st(size_t(P->G) + 1, 0);
+  std::vector<char> ok(size_t(P->G) + 1, 0);
   for (int g = P->Gc; g <= P->G; ++g) {
     K[size_t(g)] = P->lev[g].K;
-    st[size_t(g)] = P->lev[g].S64.p != nullptr;
+    ok[size_t(g)] = P->general || P->lev[g].S64.p != nullptr;
   }
-  const int gb = choose_bottom(P->opt, P->Gc, P->G, K, st);
+  const int gb = choose_bottom(P->opt, P->Gc, P->G, K, ok, P->general);
   if (gb == 0) return;
   const int D = P->d, nu1 = P->opt.nu1, nu2 = P->opt.nu2;
   hipStream_t s = P->stream;
@@ -1201,12 +1206,20 @@ static void build_bottom(Problem* P) {
     const double* w = L.wdinv64.p;
     DevBuf<double> A, M1, X, tmp, R, Pm, Y, Z;
     A.alloc(size_t(Kf * Kf));
-    hip_check(launch_fill<double>(A.p, 0.0, Kf * Kf, s), "fill");
-    hip_check(launch_dense_from_stencil(D, L.S64.p, L.J, Kf, A.p, s), "bottom");
+    R.alloc(size_t(Kc * Kf));
+    Pm.alloc(size_t(Kf * Kc));
+    if (P->general) {
+      dense_level_general(P, g, A.p);
+      restriction_dense_general(P, g, R.p);
+      hip_check(launch_transpose(R.p, Kc, Kf, Pm.p, s), "bottom");
+    } else {
+      hip_check(launch_fill<double>(A.p, 0.0, Kf * Kf, s), "fill");
+      hip_check(launch_dense_from_stencil(D, L.S64.p, L.J, Kf, A.p, s), "bottom");
+      hip_check(launch_subdivision_dense(R.p, D, P->lev[g - 1].J, L.J, false, s), "bottom");
+      hip_check(launch_subdivision_dense(Pm.p, D, P->lev[g - 1].J, L.J, true, s), "bottom");
+    }
     tmp.alloc(size_t(Kf * Kf));
     T.alloc(size_t(Kf * Kf));
-    R.alloc(size_t(Kc * Kf));
-    hip_check(launch_subdivision_dense(R.p, D, P->lev[g - 1].J, L.J, false, s), "bottom");
     Y.alloc(size_t(Kc * Kf));
     if (nu1 >= 1) {
       // M1 = W, then M1 += W (I - A M1) for each further sweep
@@ -1226,8 +1239,6 @@ static void build_bottom(Problem* P) {
     // Z = B_{g-1} Y; X = M1 + I Z
     Z.alloc(size_t(Kc * Kf));
     hip_check(launch_gemm64(Bc.p, Y.p, Nc, M, Nc, nullptr, nullptr, 0.0, 1.0, Z.p, s), "bottom");
-    Pm.alloc(size_t(Kf * Kc));
-    hip_check(launch_subdivision_dense(Pm.p, D, P->lev[g - 1].J, L.J, true, s), "bottom");
     X.alloc(size_t(Kf * Kf));
     hip_check(launch_gemm64(Pm.p, Z.p, M, M, Nc, nu1 >= 1 ? M1.p : nullptr, nullptr, 0.0, 1.0, X.p, s), "bottom");
     // post-smoothing: X += W (I - A X), nu2 times

@@ -256,6 +256,14 @@ void profile_general(Problem* P, int g, T* c, T* out, int reps, hipEvent_t e0, h
 void rhs_general(Problem* P, double* b);
 void diag_general(Problem* P, int g);
 void coarse_matrix_general(Problem* P, double* A);
+// A_g of a general level, dense (lam Lambda_g + Phi_g'Phi_g from the points).
+void dense_level_general(Problem* P, int g, double* A);
+// The dense restriction I_g' (K_{g-1} x K_g) of a general level.
+void restriction_dense_general(Problem* P, int g, double* R);
+// The level from which the V-cycle is assembled as one dense operator (0:
+// none), given the level sizes K[g] and which levels can be assembled.
+int choose_bottom(const ts_options& o, int Gc, int G, const std::vector<int64_t>& K, const std::vector<char>& ok,
+                  bool general);
 void eval_general(Problem* P, const double* alpha, int64_t m, const double* xq, double* yq);
 
 }  // namespace tsmg

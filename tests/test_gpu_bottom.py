@@ -159,3 +159,50 @@ def test_not_built_where_it_cannot_apply(lib):
             assert S.bottom_level() == 0, kw
         finally:
             S.close()
+
+
+GENERAL = {
+    # (d, intervals, degrees, n, lambda, seed), level expected to carry the operator
+    "gen_d2": ((2, [40, 24], [2, 4], 20011, 1e-3, 71), 3),    # (20, 12) at level 3: K = 22 x 16 = 352
+    "gen_d3": ((3, [24, 24, 24], [2, 2, 2], 60013, 1e-2, 72), 3),   # N = 12: K = 14^3 = 2744
+    "gen_mixed_d3": ((3, [8, 4, 12], [2, 3, 4], 6001, 1e-2, 73), 2),  # (4, 2, 6): K = 6 x 5 x 10 = 300
+}
+
+
+def _general(name):
+    (d, N, q, n, lam, seed), gb = GENERAL[name]
+    w = gc.uniform_case(d, n, N[0], lam, seed)
+    w["N"] = N
+    w["q"] = q
+    return w, gb
+
+
+@pytest.mark.parametrize("name", list(GENERAL))
+def test_general_form(lib, name):
+    """The general form (degree and intervals per dimension): A_g assembled
+    densely from the points, I_g from the subdivision passes run over a
+    batch of coarse unit vectors."""
+    w, gb = _general(name)
+    make = lambda **kw: tsmg.Smoother(w["x"], w["y"], w["N"], w["lam"], lo=w["lo"], hi=w["hi"], degrees=w["q"], **kw)
+    on, off = make(), make(bottom_max_k=-1)
+    try:
+        assert on.bottom_level() == gb and off.bottom_level() == 0
+        r = np.random.default_rng(124).standard_normal(on.K())
+        z1, z0 = on.vcycle(r).cpu().numpy(), off.vcycle(r).cpu().numpy()
+        err = _energy_rel(off, z1 - z0, z0)
+        res = []
+        for S in (on, off):
+            S.set_options(tol=1e-12, max_iter=20000)
+            a, status, info = S.solve()
+            assert status == tsmg.TS_OK, info
+            res.append((a.cpu().numpy(), info["iterations"]))
+        (a1, i1), (a0, i0) = res
+        serr = _energy_rel(off, a1 - a0, a0)
+        print(name, "V-cycle energy-norm difference %.2e" % err, "iterations", i1, i0,
+              "solution difference %.2e" % serr, flush=True)
+        assert err <= 1e-9
+        assert abs(i1 - i0) <= max(1, i0 // 50)
+        assert serr <= 1e-9
+    finally:
+        on.close()
+        off.close()
